@@ -1,0 +1,614 @@
+/*
+ * labs_oracle.c -- the oracle: a plain, slow, CPU statement of everything the GPU library
+ * computes for the skew-symmetric LABS search of
+ *   J. Brest, B. Boskovic, "Computational Search of Long Skew-symmetric Binary Sequences
+ *   with High Merit Factors", arXiv:2011.00068.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the package smoke check and the CPU-baseline
+ * leg of the benchmark load this file.  The GPU library never calls, links or includes it, and
+ * the two share no code, header, table or constant generator: every constant below is written
+ * out here from its published definition.
+ *
+ * Conventions (all 0-based, as in Eq. (1)):
+ *   S = (s_0 .. s_{L-1}), s_i in {+1,-1};  bit b_i = 1  <=>  s_i = -1  (Section 4's hex rule).
+ *   Skew-symmetric: L = 2n-1, centre c = n-1, s_{c+i} = (-1)^i s_{c-i} for i = 1..c (Eq. (4),
+ *   re-indexed from the paper's 1-based form so that Table 1's sequences satisfy it).
+ *   Free symbols s_0..s_c; "flip j" (0 <= j <= c) negates s_j and its mirror s_{L-1-j}
+ *   (one symbol when j == c), which keeps the sequence skew-symmetric.
+ *   Free-bit vector x: bit j (word j/64, bit j%64) = b_j, j = 0..c.
+ *
+ * Every accumulator is int64.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_MAX_WORDS 8 /* free-bit words (64-bit) -> n <= 512 */
+
+/* ------------------------------------------------------------------------------------------
+ * Definitions (Section 1)
+ * ---------------------------------------------------------------------------------------- */
+
+/* Eq. (1): aperiodic autocorrelation C_k = sum_{i=0}^{L-k-1} s_i s_{i+k}, k = 0..L-1. */
+void ref_corr(int32_t L, const int8_t *s, int64_t *C)
+{
+    for (int32_t k = 0; k < L; k++) {
+        int64_t acc = 0;
+        for (int32_t i = 0; i + k < L; i++)
+            acc += (int64_t)s[i] * (int64_t)s[i + k];
+        C[k] = acc;
+    }
+}
+
+/* Eq. (2): ISL = sum_{k=1}^{L-1} C_k^2 (one-sided sum of squared off-peak correlations). */
+int64_t ref_isl(int32_t L, const int8_t *s)
+{
+    int64_t isl = 0;
+    for (int32_t k = 1; k < L; k++) {
+        int64_t acc = 0;
+        for (int32_t i = 0; i + k < L; i++)
+            acc += (int64_t)s[i] * (int64_t)s[i + k];
+        isl += acc * acc;
+    }
+    return isl;
+}
+
+/* Eq. (3): F = L^2 / (2 ISL).  Returns -1.0 when ISL == 0 (L == 1), where F is undefined. */
+double ref_merit(int32_t L, const int8_t *s)
+{
+    int64_t isl = ref_isl(L, s);
+    if (isl == 0)
+        return -1.0;
+    return ((double)L * (double)L) / (2.0 * (double)isl);
+}
+
+/* Section 1: peak sidelobe level PSL = max_{k=1}^{L-1} |C_k|. */
+int64_t ref_psl(int32_t L, const int8_t *s)
+{
+    int64_t psl = 0;
+    for (int32_t k = 1; k < L; k++) {
+        int64_t acc = 0;
+        for (int32_t i = 0; i + k < L; i++)
+            acc += (int64_t)s[i] * (int64_t)s[i + k];
+        if (acc < 0)
+            acc = -acc;
+        if (acc > psl)
+            psl = acc;
+    }
+    return psl;
+}
+
+/* Eq. (4), 0-based centre c = (L-1)/2: s_{c+i} = (-1)^i s_{c-i}, i = 1..c.  1 = skew. */
+int ref_is_skew(int32_t L, const int8_t *s)
+{
+    if (L < 1 || (L % 2) == 0)
+        return 0;
+    int32_t c = (L - 1) / 2;
+    for (int32_t i = 1; i <= c; i++) {
+        int32_t want = (i % 2 == 1) ? -s[c - i] : s[c - i];
+        if (s[c + i] != want)
+            return 0;
+    }
+    return 1;
+}
+
+/* Builds the skew-symmetric sequence whose free symbols s_0..s_c carry the bits of x
+ * (bit set -> -1), filling the second half by Eq. (4). */
+void ref_skew_expand(int32_t L, const uint64_t *x, int8_t *s)
+{
+    int32_t c = (L - 1) / 2;
+    for (int32_t j = 0; j <= c; j++)
+        s[j] = ((x[j / 64] >> (j % 64)) & 1u) ? -1 : 1;
+    for (int32_t i = 1; i <= c; i++)
+        s[c + i] = (i % 2 == 1) ? (int8_t)(-s[c - i]) : s[c - i];
+}
+
+/* Inverse of ref_skew_expand on the free half: x bit j = (s_j == -1).  nwords 64-bit words. */
+void ref_skew_bits(int32_t L, const int8_t *s, uint64_t *x, int32_t nwords)
+{
+    int32_t c = (L - 1) / 2;
+    for (int32_t w = 0; w < nwords; w++)
+        x[w] = 0;
+    for (int32_t j = 0; j <= c; j++)
+        if (s[j] == -1)
+            x[j / 64] |= (uint64_t)1 << (j % 64);
+}
+
+/* ------------------------------------------------------------------------------------------
+ * Section 4's hexadecimal encoding of Table 1: each hex digit is 4 bits (most significant
+ * first); leading zero bits are dropped down to length L; bit 0 -> +1, bit 1 -> -1.
+ * ---------------------------------------------------------------------------------------- */
+
+static int hex_value(char ch)
+{
+    if (ch >= '0' && ch <= '9')
+        return ch - '0';
+    if (ch >= 'A' && ch <= 'F')
+        return ch - 'A' + 10;
+    if (ch >= 'a' && ch <= 'f')
+        return ch - 'a' + 10;
+    return -1;
+}
+
+/* Returns 0 on success, -1 on a bad digit, -2 if the string has fewer than L bits,
+ * -3 if a dropped leading bit is 1. */
+int ref_hex_decode(const char *hex, int32_t L, int8_t *s)
+{
+    int32_t ndig = (int32_t)strlen(hex);
+    int32_t nbits = 4 * ndig;
+    if (nbits < L)
+        return -2;
+    int32_t drop = nbits - L;
+    for (int32_t b = 0; b < nbits; b++) {
+        int v = hex_value(hex[b / 4]);
+        if (v < 0)
+            return -1;
+        int bit = (v >> (3 - (b % 4))) & 1;
+        if (b < drop) {
+            if (bit)
+                return -3;
+            continue;
+        }
+        s[b - drop] = bit ? -1 : 1;
+    }
+    return 0;
+}
+
+/* Writes ceil(L/4) upper-case hex digits plus a terminating NUL into out (cap >= that + 1).
+ * Returns the number of digits, or -1 if cap is too small. */
+int ref_hex_encode(int32_t L, const int8_t *s, char *out, int32_t cap)
+{
+    int32_t ndig = (L + 3) / 4;
+    if (cap < ndig + 1)
+        return -1;
+    int32_t pad = 4 * ndig - L;
+    for (int32_t d = 0; d < ndig; d++) {
+        int v = 0;
+        for (int32_t q = 0; q < 4; q++) {
+            int32_t b = 4 * d + q - pad; /* index into S, negative = padding zero */
+            int bit = (b >= 0) ? (s[b] == -1) : 0;
+            v = (v << 1) | bit;
+        }
+        out[d] = "0123456789ABCDEF"[v];
+    }
+    out[ndig] = '\0';
+    return ndig;
+}
+
+/* ------------------------------------------------------------------------------------------
+ * One-flip evaluation (Section 3; Algorithm 1's "fast calculate merit factor" step).
+ * ---------------------------------------------------------------------------------------- */
+
+/* Plain definition: ISL of S with s_j and its mirror negated, recomputed from Eq. (1)-(2). */
+int64_t ref_flip_isl_brute(int32_t L, const int8_t *s, int32_t j)
+{
+    int8_t *t = (int8_t *)malloc((size_t)L);
+    memcpy(t, s, (size_t)L);
+    t[j] = (int8_t)(-t[j]);
+    if (L - 1 - j != j)
+        t[L - 1 - j] = (int8_t)(-t[L - 1 - j]);
+    int64_t isl = ref_isl(L, t);
+    free(t);
+    return isl;
+}
+
+/*
+ * Incremental evaluation from a table of the current correlations C (C[k], k = 0..L-1, as
+ * produced by ref_corr).  Derived from Eq. (1): negating the symbols of a set P negates exactly
+ * the products s_i s_{i+k} with one end in P, so C_k moves by -2 times their sum.  For a
+ * skew-symmetric S (Eq. (4)) and even k, the mirror's products equal the primary's, so for
+ * P = {j, m}, m = L-1-j, j < c, with d = m - j (the shift at which j and m pair with each
+ * other, whose product is negated twice and so does not change):
+ *     dC_k = -4 s_j ( s_{j+k} [j+k <= L-1, k != d] + s_{j-k} [j-k >= 0] ),
+ * and for the centre (P = {c}): dC_k = -4 s_c s_{c-k} [k <= c].  Odd-k correlations are 0 on
+ * every skew-symmetric sequence and stay 0.  The flipped ISL is sum over even k of
+ * (C_k + dC_k)^2.  The tests pin this against ref_flip_isl_brute on every flip.
+ */
+int64_t ref_flip_isl_incr(int32_t L, const int8_t *s, const int64_t *C, int32_t j)
+{
+    int32_t c = (L - 1) / 2;
+    int64_t isl = 0;
+    for (int32_t k = 2; k <= L - 1; k += 2) {
+        int64_t dk;
+        if (j < c) {
+            int32_t d = L - 1 - 2 * j;
+            int64_t p = (j + k <= L - 1 && k != d) ? s[j + k] : 0;
+            int64_t q = (j - k >= 0) ? s[j - k] : 0;
+            dk = -4 * (int64_t)s[j] * (p + q);
+        } else {
+            int64_t q = (k <= c) ? s[c - k] : 0;
+            dk = -4 * (int64_t)s[c] * q;
+        }
+        int64_t t = C[k] + dk;
+        isl += t * t;
+    }
+    return isl;
+}
+
+/* All n = c+1 flip scores of the skew sequence with free bits x.  brute != 0 selects the plain
+ * definition, otherwise the incremental evaluation. */
+void ref_flip_scores(int32_t L, const uint64_t *x, int64_t *out, int brute)
+{
+    int8_t *s = (int8_t *)malloc((size_t)L);
+    int64_t *C = (int64_t *)malloc(sizeof(int64_t) * (size_t)L);
+    ref_skew_expand(L, x, s);
+    ref_corr(L, s, C);
+    int32_t c = (L - 1) / 2;
+    for (int32_t j = 0; j <= c; j++)
+        out[j] = brute ? ref_flip_isl_brute(L, s, j) : ref_flip_isl_incr(L, s, C, j);
+    free(s);
+    free(C);
+}
+
+/* ------------------------------------------------------------------------------------------
+ * Counter-based random numbers: SplitMix64 (G. L. Steele, D. Lea, C. H. Flood, "Fast
+ * splittable pseudorandom number generators", OOPSLA 2014), written from its published
+ * definition: the state advances by the odd constant 0x9E3779B97F4A7C15 and each output is
+ * the state passed through the mixing function below.  ref_sm64_at(seed, i) is the i-th output
+ * (i = 0, 1, ...) of the generator started from state `seed`.
+ * ---------------------------------------------------------------------------------------- */
+
+static uint64_t sm64_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+uint64_t ref_sm64_at(uint64_t seed, uint64_t i)
+{
+    return sm64_mix(seed + (i + 1) * 0x9E3779B97F4A7C15ULL);
+}
+
+/* Start sequence of restart r of walk w (Algorithm 1's "initialize a starting skew-symmetric
+ * sequence"; the paper does not say how): free symbols i.i.d. uniform, drawn as 64-bit words
+ *   key_w = sm64_at(seed, w), key_wr = sm64_at(key_w, r), word_i = sm64_at(key_wr, i),
+ * bit j of x = bit (j % 64) of word_(j / 64), bits at j >= n cleared. */
+void ref_start_bits(int32_t L, uint64_t seed, uint32_t walk_id, uint32_t restart, uint64_t *x,
+                    int32_t nwords)
+{
+    int32_t n = (L + 1) / 2;
+    uint64_t kw = ref_sm64_at(seed, walk_id);
+    uint64_t kr = ref_sm64_at(kw, restart);
+    for (int32_t w = 0; w < nwords; w++) {
+        uint64_t v = ref_sm64_at(kr, (uint64_t)w);
+        int32_t lo = 64 * w;
+        if (lo >= n)
+            v = 0;
+        else if (n - lo < 64)
+            v &= (((uint64_t)1) << (n - lo)) - 1;
+        x[w] = v;
+    }
+}
+
+/* Zobrist key of free symbol j (A. L. Zobrist, 1970): z_j = sm64_at(0x2011000068ABCDEF, j).
+ * The hash of a state is the XOR of z_j over its set free bits. */
+uint64_t ref_zobrist(int32_t j)
+{
+    return ref_sm64_at(0x2011000068ABCDEFULL, (uint64_t)j);
+}
+
+/* ------------------------------------------------------------------------------------------
+ * The search walk (Section 3, Algorithm 1, in its self-avoiding-walk reading): at every step
+ * score all n flips of the current state, move to the best flip whose resulting state has not
+ * been visited (lowest index on ties), record it as visited, and keep the best state seen.
+ * ---------------------------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t L;
+    int32_t table_log2;     /* visited table has 2^table_log2 64-bit words */
+    uint64_t seed;
+    uint32_t walk_id;
+    uint32_t flags;         /* ORACLE_BRUTE: score flips by the plain definition;
+                               ORACLE_IDEAL: exact visited set instead of the bounded table */
+    int64_t steps;          /* iteration budget */
+    int64_t restart_period; /* 0 = never */
+    int64_t target_isl;     /* -1 = none; else stop after the first state with ISL <= target */
+    int64_t watch_isl;      /* -1 = none; else record the first step with ISL <= watch */
+} ref_walk_cfg;
+
+typedef struct {
+    int64_t best_isl, best_step, steps_done, flip_evals, hit_step, watch_step, final_isl;
+    int32_t restarts, traps;
+    uint32_t best_bits[2 * ORACLE_MAX_WORDS];  /* 32-bit words of the free bits */
+    uint32_t final_bits[2 * ORACLE_MAX_WORDS];
+} ref_walk_result;
+
+#define ORACLE_BRUTE 1u
+#define ORACLE_IDEAL 2u
+
+/* Exact visited set used with ORACLE_IDEAL: open addressing over whole free-bit vectors. */
+typedef struct {
+    uint64_t *keys; /* cap * nwords words */
+    uint8_t *used;
+    int64_t cap, count;
+    int32_t nwords;
+} ideal_set;
+
+static uint64_t ideal_hash(const uint64_t *x, int32_t nwords)
+{
+    uint64_t h = 0x12345678ULL;
+    for (int32_t w = 0; w < nwords; w++)
+        h = sm64_mix(h ^ x[w]);
+    return h;
+}
+
+static void ideal_init(ideal_set *S, int32_t nwords)
+{
+    S->nwords = nwords;
+    S->cap = 1024;
+    S->count = 0;
+    S->keys = (uint64_t *)calloc((size_t)S->cap * (size_t)nwords, sizeof(uint64_t));
+    S->used = (uint8_t *)calloc((size_t)S->cap, 1);
+}
+
+static void ideal_free(ideal_set *S)
+{
+    free(S->keys);
+    free(S->used);
+}
+
+static void ideal_clear(ideal_set *S)
+{
+    memset(S->used, 0, (size_t)S->cap);
+    S->count = 0;
+}
+
+static int ideal_contains(const ideal_set *S, const uint64_t *x)
+{
+    int64_t i = (int64_t)(ideal_hash(x, S->nwords) & (uint64_t)(S->cap - 1));
+    while (S->used[i]) {
+        if (memcmp(S->keys + i * S->nwords, x, sizeof(uint64_t) * (size_t)S->nwords) == 0)
+            return 1;
+        i = (i + 1) & (S->cap - 1);
+    }
+    return 0;
+}
+
+static void ideal_insert(ideal_set *S, const uint64_t *x);
+
+static void ideal_grow(ideal_set *S)
+{
+    ideal_set T;
+    T.nwords = S->nwords;
+    T.cap = S->cap * 2;
+    T.count = 0;
+    T.keys = (uint64_t *)calloc((size_t)T.cap * (size_t)T.nwords, sizeof(uint64_t));
+    T.used = (uint8_t *)calloc((size_t)T.cap, 1);
+    for (int64_t i = 0; i < S->cap; i++)
+        if (S->used[i])
+            ideal_insert(&T, S->keys + i * S->nwords);
+    ideal_free(S);
+    *S = T;
+}
+
+static void ideal_insert(ideal_set *S, const uint64_t *x)
+{
+    if (ideal_contains(S, x))
+        return;
+    if (2 * (S->count + 1) > S->cap)
+        ideal_grow(S);
+    int64_t i = (int64_t)(ideal_hash(x, S->nwords) & (uint64_t)(S->cap - 1));
+    while (S->used[i])
+        i = (i + 1) & (S->cap - 1);
+    S->used[i] = 1;
+    memcpy(S->keys + i * S->nwords, x, sizeof(uint64_t) * (size_t)S->nwords);
+    S->count++;
+}
+
+/* Bounded visited table (the paper's hash table HT; its size and collision handling are not
+ * stated).  Direct-mapped, one 64-bit word per slot, 0 = empty, stored word = hash | 1.
+ * Slot = the state's free bits read as an integer when they fit (n <= table_log2: exact, never
+ * evicts), otherwise the top table_log2 bits of the hash.  Insert overwrites. */
+typedef struct {
+    uint64_t *T;
+    int32_t log2;
+    int exact;
+} bounded_table;
+
+static uint64_t table_slot(const bounded_table *B, uint64_t h, const uint64_t *x)
+{
+    if (B->exact)
+        return x[0];
+    return h >> (64 - B->log2);
+}
+
+static void to_u32_words(const uint64_t *x, int32_t nwords, uint32_t *out)
+{
+    for (int32_t w = 0; w < nwords; w++) {
+        out[2 * w] = (uint32_t)(x[w] & 0xFFFFFFFFu);
+        out[2 * w + 1] = (uint32_t)(x[w] >> 32);
+    }
+}
+
+/*
+ * One walk.  trace (optional): 2 int32 per iteration, (chosen flip or -1 when trapped, ISL of
+ * the state after the iteration).  score_trace (optional): n int32 per iteration, every flip's
+ * ISL in index order.  Returns 0, or -1 on invalid arguments, -2 if an internal check fails.
+ */
+int ref_walk(const ref_walk_cfg *cfg, ref_walk_result *res, int32_t *trace, int32_t *score_trace)
+{
+    const int32_t L = cfg->L;
+    if (L < 3 || (L % 2) == 0 || cfg->steps < 0 || cfg->table_log2 < 1 || cfg->table_log2 > 30)
+        return -1;
+    const int32_t n = (L + 1) / 2, c = n - 1;
+    const int32_t nwords = (n + 63) / 64;
+    if (nwords > ORACLE_MAX_WORDS)
+        return -1;
+    const int brute = (cfg->flags & ORACLE_BRUTE) != 0;
+    const int ideal = (cfg->flags & ORACLE_IDEAL) != 0;
+
+    int8_t *s = (int8_t *)malloc((size_t)L);
+    int64_t *C = (int64_t *)malloc(sizeof(int64_t) * (size_t)L);
+    int64_t *score = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    uint64_t *z = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    uint64_t x[ORACLE_MAX_WORDS], xn[ORACLE_MAX_WORDS];
+    memset(x, 0, sizeof x);
+    memset(xn, 0, sizeof xn);
+    for (int32_t j = 0; j < n; j++)
+        z[j] = ref_zobrist(j);
+
+    bounded_table B;
+    B.log2 = cfg->table_log2;
+    B.exact = (n <= cfg->table_log2);
+    B.T = ideal ? NULL : (uint64_t *)calloc((size_t)1 << cfg->table_log2, sizeof(uint64_t));
+    ideal_set I;
+    if (ideal)
+        ideal_init(&I, nwords);
+
+    int64_t isl = 0;
+    uint64_t h = 0;
+    uint32_t restart = 0;
+    int rc = 0;
+
+    memset(res, 0, sizeof *res);
+    res->hit_step = -1;
+    res->watch_step = -1;
+
+/* (Re)start: draw the start state, compute C and ISL from scratch, clear the visited
+ * record and insert the start state (Algorithm 1's initialisation). */
+#define START_STATE()                                                                          \
+    do {                                                                                       \
+        ref_start_bits(L, cfg->seed, cfg->walk_id, restart, x, nwords);                        \
+        ref_skew_expand(L, x, s);                                                              \
+        ref_corr(L, s, C);                                                                     \
+        isl = 0;                                                                               \
+        for (int32_t k = 1; k < L; k++)                                                        \
+            isl += C[k] * C[k];                                                                \
+        h = 0;                                                                                 \
+        for (int32_t j = 0; j < n; j++)                                                        \
+            if ((x[j / 64] >> (j % 64)) & 1u)                                                  \
+                h ^= z[j];                                                                     \
+        if (ideal) {                                                                           \
+            ideal_clear(&I);                                                                   \
+            ideal_insert(&I, x);                                                               \
+        } else {                                                                               \
+            memset(B.T, 0, sizeof(uint64_t) * ((size_t)1 << B.log2));                          \
+            B.T[table_slot(&B, h, x)] = h | 1u;                                                \
+        }                                                                                      \
+    } while (0)
+
+    START_STATE();
+    res->best_isl = isl;
+    res->best_step = 0;
+    to_u32_words(x, nwords, res->best_bits);
+    if (cfg->target_isl >= 0 && isl <= cfg->target_isl)
+        res->hit_step = 0;
+    if (cfg->watch_isl >= 0 && isl <= cfg->watch_isl)
+        res->watch_step = 0;
+
+    int64_t t = 0, flips = 0;
+    while (t < cfg->steps && !(cfg->target_isl >= 0 && res->hit_step >= 0)) {
+        /* score every flip of the current state */
+        for (int32_t j = 0; j < n; j++)
+            score[j] = brute ? ref_flip_isl_brute(L, s, j) : ref_flip_isl_incr(L, s, C, j);
+        flips += n;
+        if (score_trace)
+            for (int32_t j = 0; j < n; j++)
+                score_trace[t * n + j] = (int32_t)score[j];
+
+        /* best non-visited flip, lowest index on ties */
+        int32_t jb = -1;
+        for (int32_t j = 0; j < n; j++) {
+            memcpy(xn, x, sizeof x);
+            xn[j / 64] ^= (uint64_t)1 << (j % 64);
+            uint64_t hn = h ^ z[j];
+            int visited = ideal ? ideal_contains(&I, xn) : (B.T[table_slot(&B, hn, xn)] == (hn | 1u));
+            if (visited)
+                continue;
+            if (jb < 0 || score[j] < score[jb])
+                jb = j;
+        }
+
+        if (jb < 0) {
+            /* every neighbour visited: restart from a fresh start state */
+            res->traps++;
+            res->restarts++;
+            restart++;
+            START_STATE();
+            t++;
+            if (trace) {
+                trace[2 * t - 2] = -1;
+                trace[2 * t - 1] = (int32_t)isl;
+            }
+            continue;
+        }
+
+        /* commit the move */
+        s[jb] = (int8_t)(-s[jb]);
+        if (jb != c)
+            s[L - 1 - jb] = (int8_t)(-s[L - 1 - jb]);
+        x[jb / 64] ^= (uint64_t)1 << (jb % 64);
+        h ^= z[jb];
+        ref_corr(L, s, C);
+        isl = 0;
+        for (int32_t k = 1; k < L; k++)
+            isl += C[k] * C[k];
+        if (isl != score[jb]) {
+            rc = -2;
+            break;
+        }
+        if (ideal)
+            ideal_insert(&I, x);
+        else
+            B.T[table_slot(&B, h, x)] = h | 1u;
+        t++;
+        if (trace) {
+            trace[2 * t - 2] = jb;
+            trace[2 * t - 1] = (int32_t)isl;
+        }
+        if (isl < res->best_isl) {
+            res->best_isl = isl;
+            res->best_step = t;
+            to_u32_words(x, nwords, res->best_bits);
+        }
+        if (cfg->target_isl >= 0 && res->hit_step < 0 && isl <= cfg->target_isl)
+            res->hit_step = t;
+        if (cfg->watch_isl >= 0 && res->watch_step < 0 && isl <= cfg->watch_isl)
+            res->watch_step = t;
+        /* periodic restart (lssOrel-style, Section 2), only if the walk goes on */
+        if (cfg->restart_period > 0 && t % cfg->restart_period == 0 && t < cfg->steps &&
+            !(cfg->target_isl >= 0 && res->hit_step >= 0)) {
+            res->restarts++;
+            restart++;
+            START_STATE();
+        }
+    }
+#undef START_STATE
+
+    res->steps_done = t;
+    res->flip_evals = flips;
+    res->final_isl = isl;
+    to_u32_words(x, nwords, res->final_bits);
+
+    free(s);
+    free(C);
+    free(score);
+    free(z);
+    if (ideal)
+        ideal_free(&I);
+    else
+        free(B.T);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------------------------
+ * Exhaustive skew-symmetric enumeration (Eq. (4) leaves 2^n sequences; Section 1 notes the
+ * search-space reduction).  out[x] = ISL of the sequence with free bits x, x = 0..2^n - 1.
+ * ---------------------------------------------------------------------------------------- */
+int ref_enum_skew(int32_t L, int64_t *out)
+{
+    if (L < 1 || (L % 2) == 0)
+        return -1;
+    int32_t n = (L + 1) / 2;
+    if (n > 30)
+        return -1;
+    int8_t *s = (int8_t *)malloc((size_t)L);
+    for (uint64_t x = 0; x < ((uint64_t)1 << n); x++) {
+        uint64_t xw[1] = {x};
+        ref_skew_expand(L, xw, s);
+        out[x] = ref_isl(L, s);
+    }
+    free(s);
+    return 0;
+}

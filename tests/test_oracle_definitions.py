@@ -1,0 +1,219 @@
+"""Pins of the oracle's definitions (Eq. (1)-(4), PSL, Section 4's hex rule, SplitMix64)
+against values fixed by the paper and by mathematics, not by the oracle itself."""
+import itertools
+import math
+import random
+
+import numpy as np
+import pytest
+
+from oracle import oracle as o
+from tests import table1
+
+# Table 1 rows whose printed F no integer ISL of the printed sequence reproduces (see the design doc,
+# "readings"): the computed ISL is asserted instead.
+TABLE1_ERRATA_ISL = {281: 4604, 283: 4837}
+
+
+def test_table1_has_52_odd_lengths():
+    rows = table1.rows()
+    assert [r["L"] for r in rows] == list(range(201, 304, 2))
+
+
+@pytest.mark.parametrize("row", table1.rows(), ids=lambda r: f"L{r['L']}")
+def test_table1_row(row):
+    L = row["L"]
+    s = o.hex_decode(row["hex"], L)
+    assert len(s) == L
+    # Eq. (4) holds for every printed sequence, and with it C_k = 0 for odd k.
+    assert o.is_skew(s)
+    C = o.corr(s)
+    assert np.all(C[1::2] == 0)
+    # Printed PSL (Section 1's definition) reproduced exactly.
+    assert o.psl(s) == row["PSL"]
+    isl = o.isl(s)
+    if L in TABLE1_ERRATA_ISL:
+        assert isl == TABLE1_ERRATA_ISL[L]
+        # the printed F is not the F of the printed sequence
+        assert f"{L * L / (2 * isl):.4f}" != row["F"]
+    else:
+        F = o.merit(s)
+        assert f"{F:.4f}" == row["F"], (L, F, row["F"])
+    # Section 4's encoding round-trips.
+    assert o.hex_encode(s).lstrip("0") == row["hex"].lstrip("0")
+
+
+def test_table1_errata_281_not_reachable_by_any_isl():
+    # Printed F = 8.5763 at L = 281: no integer ISL gives L^2 / (2 ISL) rounding to it.
+    L = 281
+    hits = [i for i in range(4500, 4700) if f"{L * L / (2 * i):.4f}" == "8.5763"]
+    assert hits == []
+
+
+def test_figure1_sequence_numbers():
+    # Section 2 / Figure 1: the L = 213 sequence has F = 9.5393, PSL = 11 and an NPSL of
+    # -25.74 dB (20 log10(PSL / L)); it is Table 1's L = 213 row.
+    row = [r for r in table1.rows() if r["L"] == 213][0]
+    s = o.hex_decode(row["hex"], 213)
+    assert f"{o.merit(s):.4f}" == "9.5393"
+    assert o.psl(s) == 11
+    assert f"{20 * math.log10(o.psl(s) / 213):.2f}" == "-25.74"
+
+
+def test_barker13_worked_case():
+    # The length-13 Barker sequence is skew-symmetric; its off-peak C_k alternate 0, 1, ...
+    s = np.array([1, 1, 1, 1, 1, -1, -1, 1, 1, -1, 1, -1, 1], dtype=np.int8)
+    assert o.is_skew(s)
+    C = o.corr(s)
+    assert list(C[1:]) == [0, 1] * 6
+    assert o.isl(s) == 6
+    assert o.merit(s) == pytest.approx(169 / 12, rel=0, abs=1e-15)
+    assert o.psl(s) == 1
+
+
+def test_barker11_and_short_barkers():
+    # Barker sequences have every off-peak |C_k| <= 1, hence PSL = 1.
+    barkers = {
+        3: [1, 1, -1],
+        5: [1, 1, 1, -1, 1],
+        7: [1, 1, 1, -1, -1, 1, -1],
+        11: [1, 1, 1, -1, -1, -1, 1, -1, -1, 1, -1],
+    }
+    for L, seq in barkers.items():
+        s = np.array(seq, dtype=np.int8)
+        C = o.corr(s)
+        assert np.all(np.abs(C[1:]) <= 1)
+        assert o.isl(s) == int(np.sum(C[1:] ** 2))
+        assert o.psl(s) == 1
+
+
+def test_corr_matches_numpy_correlate():
+    rng = np.random.default_rng(7)
+    for L in [1, 2, 3, 10, 31, 64, 101, 255]:
+        s = rng.choice(np.array([-1, 1], dtype=np.int8), size=L)
+        full = np.correlate(s.astype(np.int64), s.astype(np.int64), mode="full")
+        # full[L-1+k] = sum_i s_{i+k} s_i = C_k
+        assert np.array_equal(o.corr(s), full[L - 1:])
+        assert o.isl(s) == int(np.sum(full[L:] ** 2))
+
+
+def test_merit_undefined_for_L1():
+    assert o.isl(np.array([1], dtype=np.int8)) == 0
+    assert o.merit(np.array([1], dtype=np.int8)) == -1.0
+    assert o.merit(np.array([1, 1], dtype=np.int8)) == pytest.approx(2.0)
+
+
+def _literal_skew(s):
+    # Eq. (4) as printed, with 1-based indices shifted by one: L = 2n - 1, and
+    # s_{n+i} = (-1)^i s_{n-i} for i = 1..n-1 in 1-based indexing.
+    L = len(s)
+    n = (L + 1) // 2
+    one = [None] + list(s)  # one[1..L]
+    return all(one[n + i] == ((-1) ** i) * one[n - i] for i in range(1, n))
+
+
+def test_skew_expand_is_exactly_the_skew_set():
+    # Brute force over all 2^L sequences: the literal Eq. (4) check accepts exactly the 2^n
+    # expansions of free-bit vectors, and the oracle's skew test agrees with it.
+    for L in [3, 5, 7, 9, 11]:
+        n = (L + 1) // 2
+        expanded = {tuple(o.skew_expand(L, x)) for x in range(1 << n)}
+        assert len(expanded) == 1 << n
+        literal = set()
+        for bits in itertools.product([1, -1], repeat=L):
+            if _literal_skew(bits):
+                literal.add(tuple(bits))
+            assert o.is_skew(np.array(bits, dtype=np.int8)) == _literal_skew(bits)
+        assert literal == expanded
+        for x in range(1 << n):
+            assert o.skew_bits(o.skew_expand(L, x)) == x
+
+
+def test_search_space_is_2_pow_n():
+    # Section 1: the skew restriction leaves about 2^(L/2) sequences; exactly 2^n, n = (L+1)/2.
+    for L in [3, 5, 7, 9]:
+        count = sum(_literal_skew(b) for b in itertools.product([1, -1], repeat=L))
+        assert count == 2 ** ((L + 1) // 2)
+
+
+def _isl_all(L):
+    # ISL of all 2^L sequences via numpy, independent of the oracle.
+    idx = np.arange(1 << L, dtype=np.int64)
+    S = 1 - 2 * ((idx[:, None] >> np.arange(L)[None, :]) & 1)
+    isl = np.zeros(1 << L, dtype=np.int64)
+    for k in range(1, L):
+        Ck = np.sum(S[:, : L - k] * S[:, k:], axis=1)
+        isl += Ck * Ck
+    return S, isl
+
+
+def test_enumeration_matches_brute_force_over_all_sequences():
+    # Exhaustive skew enumeration agrees with a brute-force pass over all 2^L sequences
+    # filtered by the literal Eq. (4).
+    for L in [5, 7, 9, 11, 13, 15]:
+        S, isl_all = _isl_all(L)
+        n = (L + 1) // 2
+        c = n - 1
+        skew_mask = np.ones(1 << L, dtype=bool)
+        for i in range(1, c + 1):
+            skew_mask &= S[:, c + i] == ((-1) ** i) * S[:, c - i]
+        brute_vals = np.sort(isl_all[skew_mask])
+        enum_vals = np.sort(o.enum_skew(L))
+        assert np.array_equal(brute_vals, enum_vals)
+
+
+def test_enumeration_barker_lengths_are_optimal():
+    # The Barker sequences of lengths 11 and 13 are skew-symmetric with ISL 5 and 6; no
+    # sequence of those lengths does better, so the skew minimum is 5 and 6.
+    assert int(o.enum_skew(11).min()) == 5
+    assert int(o.enum_skew(13).min()) == 6
+
+
+def test_invariants_preserve_isl_and_skewness():
+    # Negation, reversal and alternation s_i -> (-1)^i s_i leave every |C_k| unchanged and map
+    # skew-symmetric sequences to skew-symmetric ones.
+    rng = random.Random(3)
+    for L in [3, 7, 31, 101, 255, 303]:
+        n = (L + 1) // 2
+        for _ in range(3):
+            s = o.skew_expand(L, rng.getrandbits(n))
+            base = o.isl(s)
+            alt = (s * np.array([(-1) ** i for i in range(L)], dtype=np.int8)).astype(np.int8)
+            for t in (-s, s[::-1].copy(), alt):
+                t = np.ascontiguousarray(t.astype(np.int8))
+                assert o.isl(t) == base
+                assert o.is_skew(t)
+
+
+def test_odd_shifts_vanish_on_skew_sequences():
+    rng = random.Random(11)
+    for L in range(3, 304, 2):
+        n = (L + 1) // 2
+        s = o.skew_expand(L, rng.getrandbits(n))
+        assert np.all(o.corr(s)[1::2] == 0)
+
+
+def test_hex_decode_rejects_bad_input():
+    with pytest.raises(ValueError):
+        o.hex_decode("F", 3)  # dropped leading bit is 1
+    with pytest.raises(ValueError):
+        o.hex_decode("0", 5)  # too short
+    with pytest.raises(ValueError):
+        o.hex_decode("0G", 5)
+
+
+def test_splitmix64_published_vector():
+    # First outputs of SplitMix64 started from state 0, as produced by the generator's
+    # published reference implementation.
+    assert o.sm64_at(0, 0) == 0xE220A8397B1DCDAF
+    assert o.sm64_at(0, 1) == 0x6E789E6AA1B965F4
+    assert o.sm64_at(0, 2) == 0x06C45D188009454F
+
+
+def test_start_bits_are_masked_and_distinct():
+    for L in [3, 31, 101, 255, 303]:
+        n = (L + 1) // 2
+        xs = {o.start_bits(L, 2011000068, w, 0) for w in range(64)}
+        assert len(xs) == min(64, 1 << n)
+        assert all(x < (1 << n) for x in xs)
+        assert o.start_bits(L, 5, 1, 0) != o.start_bits(L, 5, 1, 1)
