@@ -1,0 +1,272 @@
+/*
+ * labs.h -- C ABI of liblabs, a gfx950 (MI355X) implementation of the hot path of the
+ * stochastic skew-symmetric LABS search of
+ *   J. Brest, B. Boskovic, "Computational Search of Long Skew-symmetric Binary Sequences with
+ *   High Merit Factors", arXiv:2011.00068.
+ *
+ * Vocabulary (the paper's notation, 0-based indices):
+ *   S = (s_0 .. s_{L-1}), s_i in {+1,-1}                                  (Section 1)
+ *   C_k = sum_{i=0}^{L-k-1} s_i s_{i+k}                                   (Eq. (1))
+ *   ISL = sum_{k=1}^{L-1} C_k^2                                           (Eq. (2))
+ *   F   = L^2 / (2 ISL)                                                   (Eq. (3))
+ *   skew-symmetric: L = 2n-1, centre c = n-1, s_{c+i} = (-1)^i s_{c-i}    (Eq. (4), re-indexed
+ *   from the paper's 1-based form; Table 1's sequences satisfy this reading)
+ *   free bits x: bit j (32-bit word j/32, bit j%32) is 1 <=> s_j = -1, j = 0..c (the paper's
+ *   0 -> +1, 1 -> -1 convention of Section 4).
+ *   flip j (0 <= j <= c): negate s_j and its mirror s_{L-1-j} (one symbol when j == c).
+ *
+ * Conventions for every entry point:
+ *   - Return value: LABS_OK (0) or a negative LABS_E* code; nothing throws or aborts across the
+ *     ABI.  labs_strerror() names a code; labs_last_error() gives a message for the calling
+ *     thread's last failure.
+ *   - "host" pointers are ordinary CPU memory owned by the caller; the library copies out of /
+ *     into them before returning.  "device" pointers are HIP device memory (hipMalloc or a torch
+ *     CUDA tensor) owned by the caller; the library only reads / writes them.
+ *   - stream: a hipStream_t passed as void*; NULL = the default (null) stream.  Entry points
+ *     whose name ends in _dev are asynchronous on that stream unless stated otherwise; all
+ *     others are synchronous.
+ *   - Every computation runs in the library's gfx950 kernels; there is no CPU fallback.  A
+ *     missing or unusable GPU returns LABS_EDEVICE.
+ */
+#ifndef LABS_H
+#define LABS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LABS_OK 0
+#define LABS_EINVAL (-1)     /* bad argument (size, range, symbol not +1/-1, NULL pointer) */
+#define LABS_ENOTSKEW (-2)   /* a skew-only entry point got a sequence that violates Eq. (4) */
+#define LABS_ENOMEM (-3)     /* device or host allocation failed, or request above a budget */
+#define LABS_EPENDING (-4)   /* job not finished yet (labs_search_poll) */
+#define LABS_ENOTFOUND (-5)  /* unknown job id */
+#define LABS_EDEVICE (-6)    /* HIP runtime error / no usable gfx950 device */
+#define LABS_EDOM (-7)       /* result undefined (F for ISL = 0, i.e. L = 1) */
+#define LABS_ECANCELLED (-8) /* job was cancelled */
+
+/* Largest L accepted by the walk entry points (n = (L+1)/2 <= 192 free symbols). */
+#define LABS_WALK_L_MAX 383
+/* 32-bit words of a free-bit vector in the walk structures. */
+#define LABS_X_WORDS 6
+
+const char *labs_strerror(int status);
+const char *labs_last_error(void);
+
+/* Device this library runs on: fills name (NUL-terminated, cap bytes), compute-unit count and
+ * shader clock (kHz).  Returns LABS_EDEVICE when no gfx950 device is visible. */
+int labs_device_info(char *name, int32_t cap, int32_t *compute_units, int32_t *clock_khz);
+
+/* ---------------------------------------------------------------------------------------------
+ * Definitions of Section 1.
+ * ------------------------------------------------------------------------------------------- */
+
+/* ISL of one sequence (Eq. (2), with C_k of Eq. (1)).  s: host, L int8 symbols, each +1 or -1
+ * (else LABS_EINVAL).  Any 1 <= L <= 65535.  isl_out: host. */
+int labs_isl(int32_t L, const int8_t *s, int64_t *isl_out);
+
+/* Merit factor of one sequence (Eq. (3)).  As labs_isl; L == 1 (ISL = 0) gives LABS_EDOM. */
+int labs_merit(int32_t L, const int8_t *s, double *F_out);
+
+/* Batched Eq. (1)-(3) and the PSL of Section 1 (max_{k>=1} |C_k|) for `count` sequences of
+ * length L stored back to back (row r at s_dev + r*L).  Device buffers: s_dev (count*L int8),
+ * isl_dev (count int64), F_dev (count double, -1.0 where ISL = 0; may be NULL), psl_dev (count
+ * int32; may be NULL), corr_dev (count*L int32 holding C_0..C_{L-1}; may be NULL).  Symbols
+ * outside {+1,-1} are not checked on this path (the host entry points check them); 1 <= L <=
+ * 65535.  Asynchronous on stream. */
+int labs_isl_batch_dev(int32_t L, int32_t count, const int8_t *s_dev, int64_t *isl_dev,
+                       double *F_dev, int32_t *psl_dev, int32_t *corr_dev, void *stream);
+
+/* Exhaustive enumeration of the 2^n skew-symmetric sequences of odd length L (Eq. (4); the
+ * search-space reduction of Section 1).  isl_dev: device, 2^n int32; entry x is the ISL of the
+ * sequence whose free bits are x.  Odd 3 <= L <= 47 (n <= 24).  Asynchronous on stream. */
+int labs_enum_skew_dev(int32_t L, int32_t *isl_dev, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * One-flip evaluation (Section 3; Algorithm 1's fast merit-factor step).
+ * ------------------------------------------------------------------------------------------- */
+
+/* Scores of every flip of `count` skew-symmetric states of odd length L, 3 <= L <=
+ * LABS_WALK_L_MAX: scores_dev[r*n + j] = ISL of state r with flip j applied, computed from the
+ * state's correlation table as the walk does.  x_dev: device, count * LABS_X_WORDS uint32
+ * (bits at j >= n must be 0, else LABS_EINVAL is not detected: they are ignored).  variant:
+ * LABS_VARIANT_* below.  Asynchronous on stream. */
+int labs_flip_scores_dev(int32_t L, int32_t count, const uint32_t *x_dev, int32_t *scores_dev,
+                         int32_t variant, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * The search walk (Section 3, Algorithm 1, read as a self-avoiding walk over skew-symmetric
+ * sequences): at every step score all n flips of the current state, move to the lowest-ISL flip
+ * whose state is not in the walk's visited table (lowest j on ties), insert it, and keep the
+ * best state.  Walks are independent (the paper's runs are, Section 4).  The readings that fix
+ * what the paper leaves open (start states, table, ties, restarts, stop rules) are:
+ *   - start state of restart r of walk w: free bits drawn from SplitMix64: key_w =
+ *     sm(seed, walk_id), key_r = sm(key_w, r), word_i = sm(key_r, i), where sm(s, i) is the
+ *     i-th output (from 0) of SplitMix64 started at state s; bit j of x = bit j%64 of word j/64.
+ *   - visited table: 2^table_log2 64-bit words per walk, 0 = empty, entry = hash | 1, where
+ *     hash = XOR of z_j over set free bits and z_j = sm(0x2011000068ABCDEF, j).  Slot = x read
+ *     as an integer when n <= table_log2 (exact, never evicts), else the top table_log2 bits of
+ *     the hash; an insert overwrites.  The start state is inserted; so is every committed state.
+ *   - every step scores n flips (n flip evaluations, the paper's speed unit of Section 3); if
+ *     every flip leads to a visited state the walk restarts (a trap; the step still counts).
+ *   - best: strict improvement only (the first best is kept); restart states do not update it.
+ *   - after a committed step t: if ISL <= target_isl the walk records hit_step = t and stops;
+ *     if ISL <= watch_isl it records watch_step = t (first time) and goes on; if the budget
+ *     `steps` is reached it stops; otherwise if restart_period > 0 and t % restart_period == 0
+ *     it restarts.  A start state (t = 0) that already meets target / watch records step 0.
+ * ------------------------------------------------------------------------------------------- */
+
+typedef struct labs_walk_cfg {
+    int32_t L;              /* odd, 3 <= L <= LABS_WALK_L_MAX */
+    int32_t table_log2;     /* 1..30; visited table of 2^table_log2 words (16 = 512 KiB) */
+    uint64_t seed;          /* start-state generator seed */
+    uint32_t walk_id;       /* start-state stream id */
+    uint32_t flags;         /* 0, or LABS_TRACE and/or LABS_TRACE_SCORES */
+    int64_t steps;          /* step budget, >= 0 */
+    int64_t restart_period; /* 0 = never */
+    int64_t target_isl;     /* -1 = none */
+    int64_t watch_isl;      /* -1 = none */
+} labs_walk_cfg;
+
+#define LABS_TRACE 1u        /* record (chosen flip or -1 on a trap, ISL after the step) */
+#define LABS_TRACE_SCORES 2u /* record all n flip scores of every step */
+
+typedef struct labs_walk_result {
+    int64_t best_isl;   /* lowest ISL seen */
+    int64_t best_step;  /* step at which it was first reached (0 = start state) */
+    int64_t steps_done; /* steps taken */
+    int64_t flip_evals; /* n per step */
+    int64_t hit_step;   /* first step with ISL <= target_isl, else -1 */
+    int64_t watch_step; /* first step with ISL <= watch_isl, else -1 */
+    int64_t final_isl;  /* ISL of the state the walk ended in */
+    int32_t restarts;   /* restarts of any cause */
+    int32_t traps;      /* restarts caused by an all-visited neighbourhood */
+    uint32_t best_bits[LABS_X_WORDS];  /* free bits of the best state */
+    uint32_t final_bits[LABS_X_WORDS]; /* free bits of the final state */
+} labs_walk_result;
+
+/* Kernel variants: results never depend on the choice. */
+#define LABS_VARIANT_AUTO 0     /* autotuned (labs_autotune cache, else the default) */
+#define LABS_VARIANT_BITSLICE 1 /* bit-sliced correlation table, popcount scoring */
+#define LABS_VARIANT_DIRECT 2   /* int8 sequence + int32 table in LDS, direct sum of squares */
+
+typedef struct labs_plan_opts {
+    int32_t variant;          /* LABS_VARIANT_* */
+    int32_t waves_per_block;  /* walks per workgroup: 0 = auto, else 1, 2, 4 or 8 */
+    int32_t probe_width;      /* visited-table probes issued together: 0 = auto, else 1..4 */
+    int32_t plain;            /* 1 = one launch per walk, serialised (comparison form) */
+    int64_t steps_per_launch; /* 0 = auto; else steps each walk advances per kernel launch */
+    int32_t use_graph;        /* 1 = capture the launches of a run in a hipGraph and replay it */
+    int32_t persistent;       /* 0 = auto; 1 = one wave per walk (the hardware schedules the
+                                 grid); 2 = a grid of resident waves that pull walks, costliest
+                                 first, from a counter until none are left */
+} labs_plan_opts;
+
+/* Runs n_walks walks (cfg: host array) to completion on the GPU and copies the results to out
+ * (host, n_walks entries).  trace (host, may be NULL): for each walk in order with LABS_TRACE,
+ * 2*steps int32 (entries past steps_done are left 0).  scores (host, may be NULL): for each walk
+ * with LABS_TRACE_SCORES, steps*n int32.  stream as above; synchronous.  Allocates and frees
+ * its device state; use the plan API to keep it resident. */
+int labs_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, labs_walk_result *out,
+                    int32_t *trace, int32_t *scores, void *stream);
+
+typedef struct labs_walk_plan labs_walk_plan;
+
+/* Allocates device state for n_walks walks (visited tables: n_walks * 2^table_log2 * 8 bytes;
+ * LABS_ENOMEM if it does not fit), uploads cfg and resolves the options (opts may be NULL =
+ * all auto).  The plan owns its device memory until labs_walk_plan_destroy. */
+int labs_walk_plan_create(int32_t n_walks, const labs_walk_cfg *cfg, const labs_plan_opts *opts,
+                          labs_walk_plan **plan);
+/* Resets every walk to its start state and runs all walks to completion, asynchronously on
+ * stream (re-running gives identical results).  Not thread-safe per plan. */
+int labs_walk_plan_run(labs_walk_plan *plan, void *stream);
+/* Waits for the plan's last run and copies results / traces out (host buffers as in
+ * labs_walk_batch; out may be NULL). */
+int labs_walk_plan_results(labs_walk_plan *plan, labs_walk_result *out, int32_t *trace,
+                           int32_t *scores);
+/* Options the plan resolved (after autotuning). */
+int labs_walk_plan_get_opts(const labs_walk_plan *plan, labs_plan_opts *opts);
+/* Average device time of the plan's last run (hipEvents on the run's stream), milliseconds,
+ * and the number of kernel launches it made. */
+int labs_walk_plan_last_timing(const labs_walk_plan *plan, double *ms, int32_t *launches);
+void labs_walk_plan_destroy(labs_walk_plan *plan);
+
+/* Times the kernel variants / launch shapes on a short synthetic walk batch at length L and
+ * stores the fastest in the autotune cache (file named by $LABS_AUTOTUNE_CACHE, default
+ * ~/.cache/liblabs_autotune.txt; entries keyed by device arch and L).  Tuning never changes
+ * results.  best (host, may be NULL) receives the winner. */
+int labs_autotune(int32_t L, int32_t n_walks, labs_plan_opts *best);
+
+/* ---------------------------------------------------------------------------------------------
+ * Serving: a request loop that admits search jobs by device memory for their walk state, keeps
+ * every admitted walk resident across kernel launches and advances all running jobs together
+ * (continuous batching).  A job = n_walks walks of one length; each walk's step budget is
+ * floor(flip_budget / (n_walks * n)); the job stops at its budget or at the first tick
+ * boundary (every steps_per_tick logical steps) after some walk reached ISL <= ISL_T, where
+ * ISL_T = floor(L^2 * den / (2 * num)) is the exact integer form of F >= num/den (Eq. (3)).
+ * Results are a function of the request alone: they do not depend on what else runs.
+ * ------------------------------------------------------------------------------------------- */
+
+typedef struct labs_server labs_server;
+
+typedef struct labs_server_opts {
+    int64_t device_mem_bytes; /* budget for resident walk state (tables + state) */
+    int32_t table_log2;       /* visited table per walk (default 16) */
+    int32_t steps_per_tick;   /* logical steps every running walk advances per tick (> 0) */
+    int32_t max_walks;        /* slot cap (0 = as many as the budget allows) */
+    int32_t reserved;
+} labs_server_opts;
+
+typedef struct labs_search_req {
+    int32_t L;             /* odd, 3 <= L <= LABS_WALK_L_MAX */
+    int32_t n_walks;       /* >= 1 */
+    uint64_t seed;         /* walk w of the job uses walk_id = w */
+    int64_t flip_budget;   /* total flip evaluations over all walks */
+    int64_t target_F_num;  /* stop threshold F >= num/den; num <= 0 = none */
+    int64_t target_F_den;
+} labs_search_req;
+
+#define LABS_JOB_QUEUED 0
+#define LABS_JOB_RUNNING 1
+#define LABS_JOB_DONE 2
+#define LABS_JOB_CANCELLED 3
+
+typedef struct labs_search_status {
+    int32_t state;        /* LABS_JOB_* */
+    int32_t best_walk;    /* walk holding best_isl (lowest id on ties) */
+    int64_t best_isl;
+    double best_F;
+    int64_t hit_step;     /* lowest step at which a walk reached ISL_T, else -1 */
+    int32_t hit_walk;     /* lowest walk id reaching it at hit_step, else -1 */
+    int32_t reserved;
+    int64_t steps_done;   /* logical steps every walk of the job has taken */
+    int64_t flip_evals;   /* sum over walks */
+    double t_submit, t_admit, t_done; /* seconds on the server's monotonic clock */
+    uint32_t best_bits[LABS_X_WORDS];
+} labs_search_status;
+
+/* Creates a server owning one GPU stream, its slot pool and a scheduler thread. */
+int labs_server_create(const labs_server_opts *opts, labs_server **srv);
+/* Queues a job (never blocks on the GPU); LABS_ENOMEM if the job could never fit the budget. */
+int labs_search_submit(labs_server *srv, const labs_search_req *req, uint64_t *job_id);
+/* LABS_OK with st filled when the job is done or cancelled; LABS_EPENDING with st filled
+ * (state QUEUED or RUNNING) otherwise; LABS_ENOTFOUND for an unknown id.  Thread-safe. */
+int labs_search_poll(labs_server *srv, uint64_t job_id, labs_search_status *st);
+/* Blocks until the job is done (or timeout_ms passes: LABS_EPENDING); timeout_ms < 0 waits. */
+int labs_search_wait(labs_server *srv, uint64_t job_id, int64_t timeout_ms,
+                     labs_search_status *st);
+/* Cancels a queued or running job; its slots are freed at the next tick.  Thread-safe. */
+int labs_search_cancel(labs_server *srv, uint64_t job_id);
+/* Server counters: ticks run, walks resident now, peak resident walks, flip evaluations done. */
+int labs_server_stats(labs_server *srv, int64_t *ticks, int32_t *resident_walks,
+                      int32_t *peak_walks, int64_t *flip_evals);
+/* Stops the scheduler (running jobs are cancelled) and frees everything. */
+void labs_server_destroy(labs_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LABS_H */

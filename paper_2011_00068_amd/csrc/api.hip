@@ -1,0 +1,723 @@
+// api.hip -- the C ABI of liblabs (include/labs.h): argument checking, device memory, launch
+// plans, hipGraph capture and the autotuner.  No computation happens on the CPU: every entry
+// point ends in the library's kernels.
+
+#include <algorithm>
+#include <cerrno>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <sys/stat.h>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace liblabs {
+
+static thread_local char g_last_error[512] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(LABS_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+    return fail(LABS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                                                                           \
+    do {                                                                                              \
+        hipError_t e_ = (expr);                                                                       \
+        if (e_ != hipSuccess)                                                                         \
+            return hip_fail(e_, what);                                                                \
+    } while (0)
+
+int check_device()
+{
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0)
+        return fail(LABS_EDEVICE, "no HIP device visible (%s)", hipGetErrorString(e));
+    return LABS_OK;
+}
+
+static std::string device_arch()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+int walk_cfg_check(const labs_walk_cfg &c, int idx)
+{
+    if (c.L < 3 || c.L > LABS_WALK_L_MAX || (c.L % 2) == 0)
+        return fail(LABS_EINVAL, "walk %d: L = %d must be odd and in [3, %d]", idx, c.L, LABS_WALK_L_MAX);
+    if (c.table_log2 < 1 || c.table_log2 > 30)
+        return fail(LABS_EINVAL, "walk %d: table_log2 = %d must be in [1, 30]", idx, c.table_log2);
+    if (c.steps < 0)
+        return fail(LABS_EINVAL, "walk %d: steps < 0", idx);
+    if (c.restart_period < 0)
+        return fail(LABS_EINVAL, "walk %d: restart_period < 0", idx);
+    if (c.target_isl < -1 || c.watch_isl < -1)
+        return fail(LABS_EINVAL, "walk %d: target_isl / watch_isl must be >= -1", idx);
+    if (c.flags & ~(LABS_TRACE | LABS_TRACE_SCORES))
+        return fail(LABS_EINVAL, "walk %d: unknown flags 0x%x", idx, c.flags);
+    if (c.steps > ((int64_t)1 << 40))
+        return fail(LABS_EINVAL, "walk %d: steps above 2^40", idx);
+    return LABS_OK;
+}
+
+} // namespace liblabs
+
+using namespace liblabs;
+
+// =============================================================================================
+// Errors, device.
+// =============================================================================================
+extern "C" const char *labs_strerror(int status)
+{
+    switch (status) {
+    case LABS_OK: return "ok";
+    case LABS_EINVAL: return "invalid argument";
+    case LABS_ENOTSKEW: return "sequence is not skew-symmetric";
+    case LABS_ENOMEM: return "out of memory";
+    case LABS_EPENDING: return "pending";
+    case LABS_ENOTFOUND: return "not found";
+    case LABS_EDEVICE: return "device error";
+    case LABS_EDOM: return "undefined result";
+    case LABS_ECANCELLED: return "cancelled";
+    default: return "unknown status";
+    }
+}
+
+extern "C" const char *labs_last_error(void) { return g_last_error; }
+
+extern "C" int labs_device_info(char *name, int32_t cap, int32_t *compute_units, int32_t *clock_khz)
+{
+    int rc = check_device();
+    if (rc)
+        return rc;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+    if (name && cap > 0) {
+        snprintf(name, (size_t)cap, "%s", prop.gcnArchName);
+    }
+    if (compute_units)
+        *compute_units = prop.multiProcessorCount;
+    if (clock_khz)
+        *clock_khz = prop.clockRate;
+    return LABS_OK;
+}
+
+// =============================================================================================
+// Definitions: labs_isl, labs_merit, labs_isl_batch_dev, labs_enum_skew_dev.
+// =============================================================================================
+static int isl_one(int32_t L, const int8_t *s, int64_t *isl_out, double *F_out)
+{
+    if (!s || L < 1 || L > 65535)
+        return fail(LABS_EINVAL, "L = %d out of [1, 65535] or NULL sequence", L);
+    for (int32_t i = 0; i < L; i++)
+        if (s[i] != 1 && s[i] != -1)
+            return fail(LABS_EINVAL, "s[%d] = %d is not +1 or -1", i, (int)s[i]);
+    int rc = check_device();
+    if (rc)
+        return rc;
+    int8_t *d_s = nullptr;
+    int64_t *d_isl = nullptr;
+    double *d_F = nullptr;
+    int64_t isl = 0;
+    double F = 0.0;
+    hipError_t e = hipMalloc(&d_s, (size_t)L);
+    if (e == hipSuccess) e = hipMalloc(&d_isl, sizeof(int64_t));
+    if (e == hipSuccess) e = hipMalloc(&d_F, sizeof(double));
+    if (e == hipSuccess) e = hipMemcpy(d_s, s, (size_t)L, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_isl_batch(L, 1, d_s, d_isl, d_F, nullptr, nullptr, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(&isl, d_isl, sizeof isl, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&F, d_F, sizeof F, hipMemcpyDeviceToHost);
+    if (d_s) (void)hipFree(d_s);
+    if (d_isl) (void)hipFree(d_isl);
+    if (d_F) (void)hipFree(d_F);
+    if (e != hipSuccess)
+        return hip_fail(e, "labs_isl");
+    if (isl_out)
+        *isl_out = isl;
+    if (F_out) {
+        if (isl == 0)
+            return fail(LABS_EDOM, "F is undefined for ISL = 0 (L = %d)", L);
+        *F_out = F;
+    }
+    return LABS_OK;
+}
+
+extern "C" int labs_isl(int32_t L, const int8_t *s, int64_t *isl_out)
+{
+    if (!isl_out)
+        return fail(LABS_EINVAL, "NULL isl_out");
+    return isl_one(L, s, isl_out, nullptr);
+}
+
+extern "C" int labs_merit(int32_t L, const int8_t *s, double *F_out)
+{
+    if (!F_out)
+        return fail(LABS_EINVAL, "NULL F_out");
+    return isl_one(L, s, nullptr, F_out);
+}
+
+extern "C" int labs_isl_batch_dev(int32_t L, int32_t count, const int8_t *s_dev, int64_t *isl_dev, double *F_dev,
+                                  int32_t *psl_dev, int32_t *corr_dev, void *stream)
+{
+    if (L < 1 || L > 65535 || count < 0 || (count > 0 && (!s_dev || !isl_dev)))
+        return fail(LABS_EINVAL, "labs_isl_batch_dev: bad arguments (L = %d, count = %d)", L, count);
+    int rc = check_device();
+    if (rc)
+        return rc;
+    HIP_TRY(launch_isl_batch(L, count, s_dev, isl_dev, F_dev, psl_dev, corr_dev, (hipStream_t)stream),
+            "labs_isl_batch_dev");
+    return LABS_OK;
+}
+
+extern "C" int labs_enum_skew_dev(int32_t L, int32_t *isl_dev, void *stream)
+{
+    if (L < 3 || L > 47 || (L % 2) == 0 || !isl_dev)
+        return fail(LABS_EINVAL, "labs_enum_skew_dev: L = %d must be odd in [3, 47]", L);
+    int rc = check_device();
+    if (rc)
+        return rc;
+    HIP_TRY(launch_enum_skew(L, isl_dev, (hipStream_t)stream), "labs_enum_skew_dev");
+    return LABS_OK;
+}
+
+extern "C" int labs_flip_scores_dev(int32_t L, int32_t count, const uint32_t *x_dev, int32_t *scores_dev,
+                                    int32_t variant, void *stream)
+{
+    if (L < 3 || L > LABS_WALK_L_MAX || (L % 2) == 0 || count < 0 || (count > 0 && (!x_dev || !scores_dev)))
+        return fail(LABS_EINVAL, "labs_flip_scores_dev: bad arguments (L = %d, count = %d)", L, count);
+    if (variant == LABS_VARIANT_AUTO)
+        variant = LABS_VARIANT_BITSLICE;
+    if (variant != LABS_VARIANT_BITSLICE && variant != LABS_VARIANT_DIRECT)
+        return fail(LABS_EINVAL, "labs_flip_scores_dev: unknown variant %d", variant);
+    int rc = check_device();
+    if (rc)
+        return rc;
+    HIP_TRY(launch_flip_scores(variant, L, count, x_dev, scores_dev, (hipStream_t)stream), "labs_flip_scores_dev");
+    return LABS_OK;
+}
+
+// =============================================================================================
+// Walk plans.
+// =============================================================================================
+struct labs_walk_plan {
+    int32_t n_walks = 0;
+    std::vector<labs_walk_cfg> cfg;
+    std::vector<WalkState> pristine;
+    labs_plan_opts opts{};
+    WalkLaunch lp{};
+    int64_t max_steps = 0;
+    int32_t launches_per_run = 0;
+    int64_t trace_records = 0; // total (int32 pairs)
+    int64_t score_entries = 0;
+    WalkState *d_states = nullptr;
+    WalkState *d_pristine = nullptr;
+    uint64_t *d_tables = nullptr;
+    int32_t *d_trace = nullptr;
+    int32_t *d_scores = nullptr;
+    int32_t *d_counter = nullptr;
+    int32_t *d_order = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t graph_stream = nullptr;
+    bool ran = false;
+    int32_t last_launches = 0;
+};
+
+namespace liblabs {
+
+static int resolve_opts(labs_walk_plan *p, const labs_plan_opts *in);
+
+static void plan_free(labs_walk_plan *p)
+{
+    if (!p)
+        return;
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->ev0) (void)hipEventDestroy(p->ev0);
+    if (p->ev1) (void)hipEventDestroy(p->ev1);
+    if (p->d_states) (void)hipFree(p->d_states);
+    if (p->d_pristine) (void)hipFree(p->d_pristine);
+    if (p->d_tables) (void)hipFree(p->d_tables);
+    if (p->d_trace) (void)hipFree(p->d_trace);
+    if (p->d_scores) (void)hipFree(p->d_scores);
+    if (p->d_counter) (void)hipFree(p->d_counter);
+    if (p->d_order) (void)hipFree(p->d_order);
+    delete p;
+}
+
+// Enqueue one full run: reset, then the walk launches.
+static hipError_t enqueue_run(labs_walk_plan *p, hipStream_t s, int32_t *launches)
+{
+    hipError_t e = launch_reset(p->d_states, p->d_pristine, p->n_walks, p->d_counter, s);
+    if (e != hipSuccess)
+        return e;
+    int32_t nl = 0;
+    if (p->opts.plain) {
+        // comparison form: one walk per launch, serialised on the stream
+        WalkLaunch lp = p->lp;
+        lp.persistent = 0;
+        lp.waves_per_block = 1;
+        for (int32_t i = 0; i < p->n_walks; i++) {
+            for (int64_t done = 0; done < p->cfg[(size_t)i].steps || done == 0; done += lp.chunk) {
+                e = launch_walk(lp, p->d_states, 1, p->d_order + i, p->d_tables, p->d_trace, p->d_scores, nullptr, s);
+                if (e != hipSuccess)
+                    return e;
+                nl++;
+                if (lp.chunk <= 0)
+                    break;
+            }
+        }
+    } else {
+        for (int32_t r = 0; r < p->launches_per_run; r++) {
+            if (r > 0 && p->lp.persistent) {
+                e = launch_zero_counter(p->d_counter, s);
+                if (e != hipSuccess)
+                    return e;
+            }
+            e = launch_walk(p->lp, p->d_states, p->n_walks, p->d_order, p->d_tables, p->d_trace, p->d_scores,
+                            p->d_counter, s);
+            if (e != hipSuccess)
+                return e;
+            nl++;
+        }
+    }
+    *launches = nl;
+    return hipSuccess;
+}
+
+} // namespace liblabs
+
+extern "C" int labs_walk_plan_create(int32_t n_walks, const labs_walk_cfg *cfg, const labs_plan_opts *opts,
+                                     labs_walk_plan **plan)
+{
+    if (!plan)
+        return fail(LABS_EINVAL, "NULL plan");
+    *plan = nullptr;
+    if (n_walks < 1 || !cfg)
+        return fail(LABS_EINVAL, "n_walks = %d must be >= 1 with a cfg array", n_walks);
+    for (int32_t i = 0; i < n_walks; i++) {
+        int rc = walk_cfg_check(cfg[i], i);
+        if (rc)
+            return rc;
+    }
+    int rc = check_device();
+    if (rc)
+        return rc;
+    labs_walk_plan *p = new labs_walk_plan();
+    p->n_walks = n_walks;
+    p->cfg.assign(cfg, cfg + n_walks);
+    p->pristine.resize((size_t)n_walks);
+    int64_t table_words = 0;
+    for (int32_t i = 0; i < n_walks; i++) {
+        const labs_walk_cfg &c = cfg[i];
+        WalkState w;
+        memset(&w, 0, sizeof w);
+        w.L = c.L;
+        w.table_log2 = c.table_log2;
+        w.seed = c.seed;
+        w.walk_id = c.walk_id;
+        w.flags = c.flags;
+        w.steps = c.steps;
+        w.restart_period = c.restart_period;
+        w.target_isl = c.target_isl;
+        w.watch_isl = c.watch_isl;
+        w.table_offset = table_words;
+        table_words += (int64_t)1 << c.table_log2;
+        const int n = (c.L + 1) / 2;
+        if (c.flags & LABS_TRACE) {
+            w.trace_offset = p->trace_records;
+            p->trace_records += c.steps;
+        } else {
+            w.trace_offset = -1;
+        }
+        if (c.flags & LABS_TRACE_SCORES) {
+            w.score_offset = p->score_entries;
+            p->score_entries += c.steps * n;
+        } else {
+            w.score_offset = -1;
+        }
+        w.step_cap = INT64_MAX;
+        w.hit_step = -1;
+        w.watch_step = -1;
+        w.status = kFresh;
+        p->pristine[(size_t)i] = w;
+        p->max_steps = std::max(p->max_steps, c.steps);
+    }
+    rc = resolve_opts(p, opts);
+    if (rc) {
+        plan_free(p);
+        return rc;
+    }
+    // walk order: costliest shape first (longest-first for mixed lengths), stable by index
+    std::vector<int32_t> order((size_t)n_walks);
+    for (int32_t i = 0; i < n_walks; i++)
+        order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return cfg[a].L > cfg[b].L;
+    });
+    if (p->opts.plain) {
+        for (int32_t i = 0; i < n_walks; i++)
+            order[(size_t)i] = i;
+    }
+    hipError_t e = hipMalloc(&p->d_states, sizeof(WalkState) * (size_t)n_walks);
+    if (e == hipSuccess) e = hipMalloc(&p->d_pristine, sizeof(WalkState) * (size_t)n_walks);
+    if (e == hipSuccess) e = hipMalloc(&p->d_tables, sizeof(uint64_t) * (size_t)table_words);
+    if (e == hipSuccess && p->trace_records > 0) e = hipMalloc(&p->d_trace, sizeof(int32_t) * 2 * (size_t)p->trace_records);
+    if (e == hipSuccess && p->score_entries > 0) e = hipMalloc(&p->d_scores, sizeof(int32_t) * (size_t)p->score_entries);
+    if (e == hipSuccess) e = hipMalloc(&p->d_counter, sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&p->d_order, sizeof(int32_t) * (size_t)n_walks);
+    if (e == hipSuccess) e = hipMemcpy(p->d_pristine, p->pristine.data(), sizeof(WalkState) * (size_t)n_walks, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_order, order.data(), sizeof(int32_t) * (size_t)n_walks, hipMemcpyHostToDevice);
+    if (e == hipSuccess && p->d_trace) e = hipMemset(p->d_trace, 0, sizeof(int32_t) * 2 * (size_t)p->trace_records);
+    if (e == hipSuccess && p->d_scores) e = hipMemset(p->d_scores, 0, sizeof(int32_t) * (size_t)p->score_entries);
+    if (e == hipSuccess) e = hipEventCreate(&p->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&p->ev1);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        plan_free(p);
+        return hip_fail(e, "labs_walk_plan_create");
+    }
+    *plan = p;
+    return LABS_OK;
+}
+
+extern "C" int labs_walk_plan_run(labs_walk_plan *p, void *stream)
+{
+    if (!p)
+        return fail(LABS_EINVAL, "NULL plan");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipEventRecord(p->ev0, s), "hipEventRecord");
+    int32_t nl = 0;
+    if (p->opts.use_graph && !p->opts.plain) {
+        if (!p->graph_exec || p->graph_stream != s) {
+            if (p->graph_exec) {
+                (void)hipGraphExecDestroy(p->graph_exec);
+                p->graph_exec = nullptr;
+            }
+            hipStream_t cap = s;
+            hipStream_t own = nullptr;
+            if (cap == nullptr) {
+                HIP_TRY(hipStreamCreate(&own), "hipStreamCreate");
+                cap = own;
+            }
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                hipError_t e2 = enqueue_run(p, cap, &nl);
+                e = hipStreamEndCapture(cap, &g);
+                if (e2 != hipSuccess)
+                    e = e2;
+            }
+            if (e == hipSuccess)
+                e = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0);
+            if (g)
+                (void)hipGraphDestroy(g);
+            if (own)
+                (void)hipStreamDestroy(own);
+            if (e != hipSuccess)
+                return hip_fail(e, "graph capture");
+            p->graph_stream = s;
+            p->launches_per_run = nl - 0; // informational
+        }
+        HIP_TRY(hipGraphLaunch(p->graph_exec, s), "hipGraphLaunch");
+        nl = p->launches_per_run;
+    } else {
+        hipError_t e = enqueue_run(p, s, &nl);
+        if (e != hipSuccess)
+            return hip_fail(e, "walk launch");
+    }
+    HIP_TRY(hipEventRecord(p->ev1, s), "hipEventRecord");
+    p->ran = true;
+    p->last_launches = nl;
+    return LABS_OK;
+}
+
+extern "C" int labs_walk_plan_results(labs_walk_plan *p, labs_walk_result *out, int32_t *trace, int32_t *scores)
+{
+    if (!p)
+        return fail(LABS_EINVAL, "NULL plan");
+    if (!p->ran)
+        return fail(LABS_EINVAL, "plan has not been run");
+    HIP_TRY(hipEventSynchronize(p->ev1), "hipEventSynchronize");
+    if (out) {
+        std::vector<WalkState> st((size_t)p->n_walks);
+        HIP_TRY(hipMemcpy(st.data(), p->d_states, sizeof(WalkState) * st.size(), hipMemcpyDeviceToHost), "results copy");
+        for (int32_t i = 0; i < p->n_walks; i++) {
+            const WalkState &w = st[(size_t)i];
+            labs_walk_result &r = out[i];
+            memset(&r, 0, sizeof r);
+            r.best_isl = w.best_isl;
+            r.best_step = w.best_step;
+            r.steps_done = w.t;
+            r.flip_evals = w.flips;
+            r.hit_step = w.hit_step;
+            r.watch_step = w.watch_step;
+            r.final_isl = w.isl;
+            r.restarts = w.restarts;
+            r.traps = w.traps;
+            for (int k = 0; k < kXWords; k++) {
+                r.best_bits[k] = w.best_x[k];
+                r.final_bits[k] = w.x[k];
+            }
+        }
+    }
+    if (trace && p->trace_records > 0)
+        HIP_TRY(hipMemcpy(trace, p->d_trace, sizeof(int32_t) * 2 * (size_t)p->trace_records, hipMemcpyDeviceToHost),
+                "trace copy");
+    if (scores && p->score_entries > 0)
+        HIP_TRY(hipMemcpy(scores, p->d_scores, sizeof(int32_t) * (size_t)p->score_entries, hipMemcpyDeviceToHost),
+                "score copy");
+    return LABS_OK;
+}
+
+extern "C" int labs_walk_plan_get_opts(const labs_walk_plan *p, labs_plan_opts *opts)
+{
+    if (!p || !opts)
+        return fail(LABS_EINVAL, "NULL argument");
+    *opts = p->opts;
+    return LABS_OK;
+}
+
+extern "C" int labs_walk_plan_last_timing(const labs_walk_plan *p, double *ms, int32_t *launches)
+{
+    if (!p || !p->ran)
+        return fail(LABS_EINVAL, "plan has not been run");
+    HIP_TRY(hipEventSynchronize(p->ev1), "hipEventSynchronize");
+    float f = 0.f;
+    HIP_TRY(hipEventElapsedTime(&f, p->ev0, p->ev1), "hipEventElapsedTime");
+    if (ms)
+        *ms = (double)f;
+    if (launches)
+        *launches = p->last_launches;
+    return LABS_OK;
+}
+
+extern "C" void labs_walk_plan_destroy(labs_walk_plan *p)
+{
+    if (p && p->ran)
+        (void)hipEventSynchronize(p->ev1);
+    plan_free(p);
+}
+
+extern "C" int labs_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, labs_walk_result *out, int32_t *trace,
+                               int32_t *scores, void *stream)
+{
+    labs_walk_plan *p = nullptr;
+    int rc = labs_walk_plan_create(n_walks, cfg, nullptr, &p);
+    if (rc)
+        return rc;
+    rc = labs_walk_plan_run(p, stream);
+    if (!rc)
+        rc = labs_walk_plan_results(p, out, trace, scores);
+    labs_walk_plan_destroy(p);
+    return rc;
+}
+
+// =============================================================================================
+// Option resolution and the autotuner.
+// =============================================================================================
+namespace liblabs {
+
+static std::mutex g_tune_mu;
+
+static std::string cache_path()
+{
+    const char *env = getenv("LABS_AUTOTUNE_CACHE");
+    if (env && *env)
+        return env;
+    const char *home = getenv("HOME");
+    return std::string(home ? home : "/tmp") + "/.cache/liblabs_autotune.txt";
+}
+
+// cache lines: "<arch> <L> <variant> <waves_per_block> <probe_width> <persistent>"
+static bool cache_lookup(int L, labs_plan_opts *o)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::ifstream f(cache_path());
+    if (!f)
+        return false;
+    const std::string arch = device_arch();
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string a;
+        int l, v, wpb, pw, pers;
+        if (!(is >> a >> l >> v >> wpb >> pw >> pers))
+            continue;
+        if (a == arch && l == L) {
+            o->variant = v;
+            o->waves_per_block = wpb;
+            o->probe_width = pw;
+            o->persistent = pers;
+            found = true; // last entry wins
+        }
+    }
+    return found;
+}
+
+static void cache_store(int L, const labs_plan_opts &o)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const std::string path = cache_path();
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos) {
+        const std::string dir = path.substr(0, slash);
+        (void)mkdir(dir.c_str(), 0755); // best effort: the last component only
+    }
+    std::ofstream f(path, std::ios::app);
+    if (!f)
+        return;
+    f << device_arch() << " " << L << " " << o.variant << " " << o.waves_per_block << " " << o.probe_width << " "
+      << o.persistent << "\n";
+}
+
+static int resolve_opts(labs_walk_plan *p, const labs_plan_opts *in)
+{
+    labs_plan_opts o{};
+    if (in)
+        o = *in;
+    int32_t persistent = 0;
+    // shapes present
+    int shape = -2;
+    int maxL = 0;
+    for (const labs_walk_cfg &c : p->cfg) {
+        const int s = shape_for_length(c.L);
+        shape = (shape == -2 || shape == s) ? s : -1;
+        maxL = std::max(maxL, c.L);
+    }
+    labs_plan_opts tuned{};
+    const bool have = cache_lookup(maxL, &tuned);
+    if (o.variant == LABS_VARIANT_AUTO)
+        o.variant = have ? tuned.variant : LABS_VARIANT_BITSLICE;
+    if (o.variant != LABS_VARIANT_BITSLICE && o.variant != LABS_VARIANT_DIRECT)
+        return fail(LABS_EINVAL, "unknown variant %d", o.variant);
+    if (o.waves_per_block == 0)
+        o.waves_per_block = have ? tuned.waves_per_block : 1;
+    if (o.waves_per_block != 1 && o.waves_per_block != 2 && o.waves_per_block != 4 && o.waves_per_block != 8)
+        return fail(LABS_EINVAL, "waves_per_block = %d must be 0, 1, 2, 4 or 8", o.waves_per_block);
+    if (o.probe_width == 0)
+        o.probe_width = have ? tuned.probe_width : 2;
+    if (o.probe_width < 1 || o.probe_width > 4)
+        return fail(LABS_EINVAL, "probe_width = %d must be in [0, 4]", o.probe_width);
+    if (o.probe_width == 3)
+        o.probe_width = 2;
+    if (o.steps_per_launch < 0)
+        return fail(LABS_EINVAL, "steps_per_launch < 0");
+    if (o.steps_per_launch == 0)
+        o.steps_per_launch = std::max<int64_t>(p->max_steps, 1);
+    if (o.persistent == 0)
+        o.persistent = have ? tuned.persistent : 1;
+    if (o.persistent != 1 && o.persistent != 2)
+        return fail(LABS_EINVAL, "persistent = %d must be 0, 1 or 2", o.persistent);
+    persistent = o.persistent == 2;
+    p->opts = o;
+    p->lp.variant = o.variant;
+    p->lp.waves_per_block = o.waves_per_block;
+    p->lp.probe_width = o.probe_width;
+    p->lp.shape = shape;
+    p->lp.chunk = o.steps_per_launch;
+    p->lp.persistent = persistent;
+    int cus = 256;
+    {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            cus = prop.multiProcessorCount;
+    }
+    p->lp.grid_waves = std::min<int32_t>(p->n_walks, cus * 16);
+    const int64_t per = o.steps_per_launch;
+    p->launches_per_run = (int32_t)std::max<int64_t>(1, (p->max_steps + per - 1) / per);
+    return LABS_OK;
+}
+
+} // namespace liblabs
+
+extern "C" int labs_autotune(int32_t L, int32_t n_walks, labs_plan_opts *best)
+{
+    if (L < 3 || L > LABS_WALK_L_MAX || (L % 2) == 0 || n_walks < 1)
+        return fail(LABS_EINVAL, "labs_autotune: L = %d, n_walks = %d", L, n_walks);
+    int rc = check_device();
+    if (rc)
+        return rc;
+    std::vector<labs_walk_cfg> cfg((size_t)n_walks);
+    for (int32_t i = 0; i < n_walks; i++) {
+        labs_walk_cfg &c = cfg[(size_t)i];
+        memset(&c, 0, sizeof c);
+        c.L = L;
+        c.table_log2 = 16;
+        c.seed = 0x7E57ull;
+        c.walk_id = (uint32_t)i;
+        c.steps = 512;
+        c.target_isl = -1;
+        c.watch_isl = -1;
+    }
+    struct Cand { labs_plan_opts o; };
+    std::vector<Cand> cands;
+    for (int v : {LABS_VARIANT_BITSLICE, LABS_VARIANT_DIRECT})
+        for (int wpb : {1, 2, 4})
+            for (int pw : {1, 2, 4})
+                for (int pers : {1, 2}) {
+                    Cand c{};
+                    c.o.variant = v;
+                    c.o.waves_per_block = wpb;
+                    c.o.probe_width = pw;
+                    c.o.persistent = pers;
+                    cands.push_back(c);
+                }
+    double best_ms = 1e30;
+    Cand winner = cands[0];
+    for (const Cand &c : cands) {
+        labs_walk_plan *p = nullptr;
+        rc = labs_walk_plan_create(n_walks, cfg.data(), &c.o, &p);
+        if (rc)
+            return rc;
+        double total = 0.0;
+        for (int rep = 0; rep < 3; rep++) {
+            rc = labs_walk_plan_run(p, nullptr);
+            double ms = 0.0;
+            if (!rc)
+                rc = labs_walk_plan_last_timing(p, &ms, nullptr);
+            if (rc) {
+                labs_walk_plan_destroy(p);
+                return rc;
+            }
+            if (rep > 0)
+                total += ms;
+        }
+        labs_walk_plan_destroy(p);
+        if (total < best_ms) {
+            best_ms = total;
+            winner = c;
+        }
+    }
+    cache_store(L, winner.o);
+    if (best)
+        *best = winner.o;
+    return LABS_OK;
+}

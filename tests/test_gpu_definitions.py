@@ -1,0 +1,133 @@
+"""GPU parity of the batched definitions (Eq. (1)-(3), PSL), the skew enumeration and the
+one-flip evaluation against the oracle, through the C ABI."""
+import random
+
+import numpy as np
+import pytest
+
+from oracle import oracle as o
+from tests import table1
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def labs():
+    import paper_2011_00068_amd as labs
+
+    labs.lib()
+    return labs
+
+
+def _rand_seq(rng, L):
+    return np.array([rng.choice((-1, 1)) for _ in range(L)], dtype=np.int8)
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 31, 32, 33, 63, 64, 65, 101, 255, 256, 303, 1000, 4097])
+def test_isl_batch_matches_oracle(labs, L):
+    rng = random.Random(L)
+    count = 7
+    seqs = np.stack([_rand_seq(rng, L) for _ in range(count)])
+    dev = torch.from_numpy(seqs).cuda()
+    isl, F, psl, corr = labs.isl_batch(dev, with_corr=True)
+    torch.cuda.synchronize()
+    isl, F, psl, corr = isl.cpu().numpy(), F.cpu().numpy(), psl.cpu().numpy(), corr.cpu().numpy()
+    for r in range(count):
+        assert isl[r] == o.isl(seqs[r])
+        assert np.array_equal(corr[r], o.corr(seqs[r]))
+        assert psl[r] == (o.psl(seqs[r]) if L > 1 else 0)
+        if L > 1:
+            assert F[r] == pytest.approx(o.merit(seqs[r]), rel=1e-15)
+        else:
+            assert F[r] == -1.0
+
+
+def test_isl_batch_table1(labs):
+    rows = table1.rows()
+    by_len = {}
+    for r in rows:
+        by_len.setdefault(r["L"], []).append(o.hex_decode(r["hex"], r["L"]))
+    for L, seqs in by_len.items():
+        dev = torch.from_numpy(np.stack(seqs)).cuda()
+        isl, F, psl, _ = labs.isl_batch(dev)
+        for i, s in enumerate(seqs):
+            assert int(isl[i]) == o.isl(s)
+            assert int(psl[i]) == o.psl(s)
+
+
+def test_isl_batch_empty(labs):
+    dev = torch.zeros((0, 5), dtype=torch.int8, device="cuda")
+    isl, _, _, _ = labs.isl_batch(dev)
+    assert isl.numel() == 0
+
+
+def test_host_entry_points(labs):
+    s = np.array([1, 1, 1, 1, 1, -1, -1, 1, 1, -1, 1, -1, 1], dtype=np.int8)
+    assert labs.isl(s) == 6
+    assert labs.merit(s) == pytest.approx(169 / 12, rel=1e-15)
+    row = table1.rows()[6]
+    t = o.hex_decode(row["hex"], row["L"])
+    assert labs.isl(t) == o.isl(t)
+    with pytest.raises(labs.LabsError) as e:
+        labs.isl(np.array([1, 0, 1], dtype=np.int8))
+    assert e.value.code == labs.LABS_EINVAL
+    with pytest.raises(labs.LabsError) as e:
+        labs.merit(np.array([1], dtype=np.int8))
+    assert e.value.code == labs.LABS_EDOM
+    assert labs.isl(np.array([-1], dtype=np.int8)) == 0
+
+
+@pytest.mark.parametrize("L", [3, 5, 7, 9, 11, 13, 15, 17, 19, 21, 23, 25, 27, 29, 31])
+def test_enum_skew_matches_oracle(labs, L):
+    got = labs.enum_skew(L).cpu().numpy().astype(np.int64)
+    want = o.enum_skew(L)
+    assert np.array_equal(got, want)
+
+
+def test_enum_skew_l31_optimum(labs):
+    got = labs.enum_skew(31).cpu().numpy()
+    assert got.min() == 79 and int((got == 79).sum()) == 4
+
+
+def test_enum_skew_rejects_bad_length(labs):
+    with pytest.raises(labs.LabsError):
+        labs.enum_skew(32)
+    with pytest.raises(labs.LabsError):
+        labs.enum_skew(49)
+
+
+ALL_L = list(range(3, 384, 2))
+
+
+@pytest.mark.parametrize("variant", [1, 2], ids=["bitslice", "direct"])
+def test_flip_scores_every_length(labs, variant):
+    # every odd L in [3, 383], random states plus the all-+1 and all--1 states
+    for L in ALL_L:
+        n = (L + 1) // 2
+        rng = random.Random(L * 7 + variant)
+        xs = [rng.getrandbits(n) for _ in range(3)] + [0, (1 << n) - 1]
+        got = labs.flip_scores(L, xs, variant=variant).cpu().numpy()
+        for i, x in enumerate(xs):
+            want = o.flip_scores(L, x, brute=False)
+            assert np.array_equal(got[i], want), (L, i)
+
+
+def test_flip_scores_brute_force_sample(labs):
+    # a few states against the plain definition (flip and recompute Eq. (1)-(2))
+    for L in [3, 5, 31, 33, 63, 65, 67, 101, 129, 131, 193, 255, 257, 259, 303, 321, 383]:
+        n = (L + 1) // 2
+        rng = random.Random(L)
+        xs = [rng.getrandbits(n)]
+        for variant in (1, 2):
+            got = labs.flip_scores(L, xs, variant=variant).cpu().numpy()
+            assert np.array_equal(got[0], o.flip_scores(L, xs[0], brute=True)), (L, variant)
+
+
+def test_flip_scores_table1(labs):
+    for row in table1.rows()[::5]:
+        s = o.hex_decode(row["hex"], row["L"])
+        x = o.skew_bits(s)
+        got = labs.flip_scores(row["L"], [x]).cpu().numpy()[0]
+        assert np.array_equal(got, o.flip_scores(row["L"], x, brute=False))
