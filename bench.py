@@ -1,0 +1,214 @@
+"""Benchmark of the skew-symmetric LABS walk on one MI355X.
+
+A step is one whole job of the L = 255 headline workload: 16,384 independent walks from seeded
+uniform +-1 starts, random restarts every 2^20 steps, a visited table of 2^16 entries per walk,
+run until a walk reaches F >= 8.5 or the job has made 10^10 flip evaluations (4,768 steps per
+walk).  The walk state is resident in HBM before the timed region (a plan); each timed step resets
+every walk to its start state and runs the job to completion on the GPU.
+
+Printed: one JSON line with the throughput in flip evaluations per second (the paper's speed
+unit, Section 3: one evaluated flip = one function evaluation), the roofline of the walk kernel,
+the oracle timed on the host cores on a bounded sample of the same workload, the plain
+one-walk-per-launch form on a sample, and time-to-F >= 8 statistics.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+L = 255
+N = (L + 1) // 2
+WALKS = 16384
+FLIP_BUDGET = 10 ** 10
+STEPS = FLIP_BUDGET // (WALKS * N)  # 4768 steps per walk
+SEED = 2011000068
+TABLE_LOG2 = 16
+RESTART = 1 << 20
+TARGET_ISL = (L * L * 2) // (2 * 17)  # F >= 8.5  <=>  ISL <= floor(L^2 / 17) = 3825
+WATCH_ISL = (L * L * 1) // (2 * 8)  # F >= 8    <=>  ISL <= floor(L^2 / 16) = 4064
+# algorithmic int32 operations per flip evaluation: for each of the (L-1)/2 even shifts,
+# u = s_{j+k} + s_{j-k}, t = C_k + sigma_j u, acc += t^2  (one add, two multiply-adds)
+ALG_OPS_PER_FLIP = 3 * (L - 1) // 2
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz int32 VALU lane-operations per second
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+KERNEL_SOURCES = ["paper_2011_00068_amd/csrc/walk_kernels.hip", "paper_2011_00068_amd/csrc/device_common.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_L255_16384_traffic.json")
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cfgs(labs, walks, steps):
+    return [labs.make_cfg(L, SEED, w, steps=steps, table_log2=TABLE_LOG2, restart_period=RESTART,
+                          target_isl=TARGET_ISL, watch_isl=WATCH_ISL) for w in range(walks)]
+
+
+def time_to_f8(results, ms_per_job, steps):
+    """Time to the first F >= 8 state per walk: its step times the job's time per step (all walks
+    advance together).  Censored walks (no hit within the budget) count as never."""
+    import numpy as np
+
+    hit = np.array([r["watch_step"] for r in results], dtype=np.int64)
+    ok = hit >= 0
+    frac = float(ok.mean())
+    per_step_ms = ms_per_job / steps
+    out = {"threshold_F": 8.0, "isl_threshold": WATCH_ISL, "hit_fraction": frac,
+           "censored": frac < 0.5, "p50_s": None, "p99_s": None}
+    if ok.any():
+        times = np.sort(np.where(ok, hit * per_step_ms / 1000.0, np.inf))
+        p50 = times[int(0.50 * (len(times) - 1))]
+        p99 = times[int(0.99 * (len(times) - 1))]
+        out["p50_s"] = None if not np.isfinite(p50) else float(p50)
+        out["p99_s"] = None if not np.isfinite(p99) else float(p99)
+    best = min(r["best_isl"] for r in results)
+    out["best_isl"] = int(best)
+    out["best_F"] = L * L / (2.0 * best)
+    return out
+
+
+def cpu_baseline():
+    """The oracle as it stands, on a bounded sample of the workload: 4 walks per host thread, the
+    full 4,768 steps each, walks spread over a thread pool (ctypes releases the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import oracle as o
+
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    walks = 4 * threads
+    o.lib()
+
+    def one(w):
+        return o.walk(L, SEED, w, steps=STEPS, table_log2=TABLE_LOG2, restart_period=RESTART,
+                      target_isl=TARGET_ISL, watch_isl=WATCH_ISL)
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        res = list(ex.map(one, range(walks)))
+    dt = time.perf_counter() - t0
+    flips = sum(r["flip_evals"] for r in res)
+    return {"value": flips / dt, "unit": "flip-evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{walks} of the {WALKS} walks, all {STEPS} steps each, L={L}, "
+                      f"{threads} threads; {dt:.1f} s wall"}, res
+
+
+def plain_form(labs, walks=32):
+    """The plain one-walk-per-launch form: the same walks, one kernel launch per walk, serialised
+    on one stream (a sample of the job's walks)."""
+    import torch
+
+    plan = labs.WalkPlan(cfgs(labs, walks, STEPS), plain=True)
+    plan.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res = plan.results()
+    plan.close()
+    flips = sum(r["flip_evals"] for r in res)
+    per_walk_ms = dt * 1000.0 / walks
+    return {"value": flips / dt, "unit": "flip-evals/s", "walks": walks,
+            "ms_per_walk": per_walk_ms,
+            "time_to_F8": time_to_f8(res, per_walk_ms, STEPS)}, res
+
+
+def traffic_per_launch():
+    """HBM bytes per walk launch from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2011_00068_amd as labs
+
+    torch.cuda.set_device(0)
+    plan = labs.WalkPlan(cfgs(labs, WALKS, STEPS))
+    opts = plan.opts()
+    for _ in range(args.warmup):
+        plan.run()
+    torch.cuda.synchronize()
+    kernel_ms = []
+    launches = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.run()
+        ms, launches = plan.last_timing()  # waits for this run; device time of its walk launches
+        kernel_ms.append(ms)
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    res = plan.results()
+    plan.close()
+
+    flips_per_job = sum(r["flip_evals"] for r in res)
+    ms_per_step = wall_s * 1000.0 / args.steps
+    value = flips_per_job / (ms_per_step / 1000.0)
+
+    avg_kernel_ms = sum(kernel_ms) / len(kernel_ms)
+    per_launch_ms = avg_kernel_ms / max(1, launches)
+    alg_ops_per_launch = flips_per_job * ALG_OPS_PER_FLIP / max(1, launches)
+    achieved = alg_ops_per_launch / (per_launch_ms / 1000.0) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic_per_launch(),
+                "kernel": "k_walk", "kernel_ms_per_launch": per_launch_ms,
+                "alg_ops_per_flip": ALG_OPS_PER_FLIP}
+
+    line = {
+        "metric": "flip-evals/s at L=255 (batched walks, % INT32 VALU peak); p50 time-to-F>=8",
+        "value": value,
+        "unit": "flip-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "L255_16384walks_1e10flips", "L": L, "walks": WALKS,
+                   "steps_per_walk": STEPS, "table_log2": TABLE_LOG2, "restart_period": RESTART,
+                   "target_F": 8.5, "parallelism": "none (1 GPU)", "plan_opts": opts},
+        "roofline": roofline,
+        "time_to_F8": time_to_f8(res, ms_per_step, STEPS),
+    }
+    if not args.no_plain:
+        line["plain_form"], _ = plain_form(labs)
+    if not args.no_cpu:
+        line["cpu_baseline"], _ = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

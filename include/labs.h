@@ -188,8 +188,10 @@ int labs_walk_plan_results(labs_walk_plan *plan, labs_walk_result *out, int32_t 
                            int32_t *scores);
 /* Options the plan resolved (after autotuning). */
 int labs_walk_plan_get_opts(const labs_walk_plan *plan, labs_plan_opts *opts);
-/* Average device time of the plan's last run (hipEvents on the run's stream), milliseconds,
- * and the number of kernel launches it made. */
+/* Device time of the walk launches of the plan's last run (hipEvents recorded on the run's
+ * stream after the state reset and after the last walk launch; with use_graph the events
+ * bracket the whole graph, whose reset copy is a few microseconds), in milliseconds, and the
+ * number of walk-kernel launches the run made.  Waits for the run to finish. */
 int labs_walk_plan_last_timing(const labs_walk_plan *plan, double *ms, int32_t *launches);
 void labs_walk_plan_destroy(labs_walk_plan *plan);
 

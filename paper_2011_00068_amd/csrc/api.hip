@@ -242,7 +242,7 @@ struct labs_walk_plan {
     int32_t *d_scores = nullptr;
     int32_t *d_counter = nullptr;
     int32_t *d_order = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev_mid = nullptr, ev1 = nullptr; // run start, walks start, run end
     hipGraphExec_t graph_exec = nullptr;
     hipStream_t graph_stream = nullptr;
     bool ran = false;
@@ -259,6 +259,7 @@ static void plan_free(labs_walk_plan *p)
         return;
     if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
     if (p->ev0) (void)hipEventDestroy(p->ev0);
+    if (p->ev_mid) (void)hipEventDestroy(p->ev_mid);
     if (p->ev1) (void)hipEventDestroy(p->ev1);
     if (p->d_states) (void)hipFree(p->d_states);
     if (p->d_pristine) (void)hipFree(p->d_pristine);
@@ -271,11 +272,16 @@ static void plan_free(labs_walk_plan *p)
 }
 
 // Enqueue one full run: reset, then the walk launches.
-static hipError_t enqueue_run(labs_walk_plan *p, hipStream_t s, int32_t *launches)
+static hipError_t enqueue_run(labs_walk_plan *p, hipStream_t s, int32_t *launches, bool mark)
 {
     hipError_t e = launch_reset(p->d_states, p->d_pristine, p->n_walks, p->d_counter, s);
     if (e != hipSuccess)
         return e;
+    if (mark) {
+        e = hipEventRecord(p->ev_mid, s);
+        if (e != hipSuccess)
+            return e;
+    }
     int32_t nl = 0;
     if (p->opts.plain) {
         // comparison form: one walk per launch, serialised on the stream
@@ -396,6 +402,7 @@ extern "C" int labs_walk_plan_create(int32_t n_walks, const labs_walk_cfg *cfg, 
     if (e == hipSuccess && p->d_trace) e = hipMemset(p->d_trace, 0, sizeof(int32_t) * 2 * (size_t)p->trace_records);
     if (e == hipSuccess && p->d_scores) e = hipMemset(p->d_scores, 0, sizeof(int32_t) * (size_t)p->score_entries);
     if (e == hipSuccess) e = hipEventCreate(&p->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&p->ev_mid);
     if (e == hipSuccess) e = hipEventCreate(&p->ev1);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -428,7 +435,7 @@ extern "C" int labs_walk_plan_run(labs_walk_plan *p, void *stream)
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                hipError_t e2 = enqueue_run(p, cap, &nl);
+                hipError_t e2 = enqueue_run(p, cap, &nl, false);
                 e = hipStreamEndCapture(cap, &g);
                 if (e2 != hipSuccess)
                     e = e2;
@@ -444,10 +451,11 @@ extern "C" int labs_walk_plan_run(labs_walk_plan *p, void *stream)
             p->graph_stream = s;
             p->launches_per_run = nl - 0; // informational
         }
+        HIP_TRY(hipEventRecord(p->ev_mid, s), "hipEventRecord");
         HIP_TRY(hipGraphLaunch(p->graph_exec, s), "hipGraphLaunch");
         nl = p->launches_per_run;
     } else {
-        hipError_t e = enqueue_run(p, s, &nl);
+        hipError_t e = enqueue_run(p, s, &nl, true);
         if (e != hipSuccess)
             return hip_fail(e, "walk launch");
     }
@@ -509,7 +517,7 @@ extern "C" int labs_walk_plan_last_timing(const labs_walk_plan *p, double *ms, i
         return fail(LABS_EINVAL, "plan has not been run");
     HIP_TRY(hipEventSynchronize(p->ev1), "hipEventSynchronize");
     float f = 0.f;
-    HIP_TRY(hipEventElapsedTime(&f, p->ev0, p->ev1), "hipEventElapsedTime");
+    HIP_TRY(hipEventElapsedTime(&f, p->ev_mid, p->ev1), "hipEventElapsedTime");
     if (ms)
         *ms = (double)f;
     if (launches)

@@ -744,8 +744,10 @@ __device__ __forceinline__ void run_any(WalkState *ws, uint64_t *tables, int32_t
     }
 }
 
+constexpr int kMaxWavesPerBlock = 8;
+
 template <int SHAPE, bool DIRECT, int PW>
-__global__ void __launch_bounds__(256) k_walk(WalkState *__restrict__ states, int32_t n_walks,
+__global__ void __launch_bounds__(64 * kMaxWavesPerBlock) k_walk(WalkState *__restrict__ states, int32_t n_walks,
                                               const int32_t *__restrict__ order,
                                               uint64_t *__restrict__ tables, int32_t *__restrict__ trace,
                                               int32_t *__restrict__ scores, int64_t chunk,
@@ -862,6 +864,8 @@ hipError_t launch_walk(const WalkLaunch &lp, WalkState *states, int32_t n_walks,
     WalkKernel k = direct ? pick_shape<true>(lp.shape, lp.probe_width)
                           : pick_shape<false>(lp.shape, lp.probe_width);
     const int wpb = lp.waves_per_block;
+    if (wpb < 1 || wpb > kMaxWavesPerBlock)
+        return hipErrorInvalidConfiguration; // the kernel is compiled for at most 8 waves per block
     const size_t lds = (size_t)wpb * (direct ? sizeof(WaveLdsDirect) : sizeof(WaveLdsBits));
     int blocks;
     int32_t *ctr = nullptr;
