@@ -37,7 +37,7 @@ WATCH_ISL = (L * L * 1) // (2 * 8)  # F >= 8    <=>  ISL <= floor(L^2 / 16) = 40
 ALG_OPS_PER_FLIP = 3 * (L - 1) // 2
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz int32 VALU lane-operations per second
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-KERNEL_SOURCES = ["paper_2011_00068_amd/csrc/walk_kernels.hip", "paper_2011_00068_amd/csrc/device_common.hpp"]
+KERNEL_SOURCES = ["paper_2011_00068_amd/csrc/walk_impl.hpp", "paper_2011_00068_amd/csrc/device_common.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_L255_16384_traffic.json")
 
 
@@ -143,7 +143,21 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes (the reference "
+                         "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+
+        src = torch.ones(args.calibrate_copy, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.calibrate_copy, "copies": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)

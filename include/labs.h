@@ -155,7 +155,8 @@ typedef struct labs_walk_result {
 typedef struct labs_plan_opts {
     int32_t variant;          /* LABS_VARIANT_* */
     int32_t waves_per_block;  /* walks per workgroup: 0 = auto, else 1, 2, 4 or 8 */
-    int32_t probe_width;      /* visited-table probes issued together: 0 = auto, else 1..4 */
+    int32_t probe_width;      /* visited-table probes issued together: 0 = auto, 1 or 2
+                                 (3 and 4 are accepted and run as 2) */
     int32_t plain;            /* 1 = one launch per walk, serialised (comparison form) */
     int64_t steps_per_launch; /* 0 = auto; else steps each walk advances per kernel launch */
     int32_t use_graph;        /* 1 = capture the launches of a run in a hipGraph and replay it */

@@ -633,12 +633,13 @@ static int resolve_opts(labs_walk_plan *p, const labs_plan_opts *in)
         o.probe_width = have ? tuned.probe_width : 2;
     if (o.probe_width < 1 || o.probe_width > 4)
         return fail(LABS_EINVAL, "probe_width = %d must be in [0, 4]", o.probe_width);
-    if (o.probe_width == 3)
-        o.probe_width = 2;
+    if (o.probe_width > 2)
+        o.probe_width = 2; // the kernels are built for one or two probes in flight
     if (o.steps_per_launch < 0)
         return fail(LABS_EINVAL, "steps_per_launch < 0");
     if (o.steps_per_launch == 0)
         o.steps_per_launch = std::max<int64_t>(p->max_steps, 1);
+    o.steps_per_launch = std::min<int64_t>(o.steps_per_launch, (int64_t)1 << 30); // kernel limit
     if (o.persistent == 0)
         o.persistent = have ? tuned.persistent : 1;
     if (o.persistent != 1 && o.persistent != 2)
@@ -689,7 +690,7 @@ extern "C" int labs_autotune(int32_t L, int32_t n_walks, labs_plan_opts *best)
     std::vector<Cand> cands;
     for (int v : {LABS_VARIANT_BITSLICE, LABS_VARIANT_DIRECT})
         for (int wpb : {1, 2, 4})
-            for (int pw : {1, 2, 4})
+            for (int pw : {1, 2})
                 for (int pers : {1, 2}) {
                     Cand c{};
                     c.o.variant = v;

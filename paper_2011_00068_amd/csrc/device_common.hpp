@@ -76,46 +76,38 @@ constexpr int kRowShr8 = 0x118;
 constexpr int kRowBcast15 = 0x142;
 constexpr int kRowBcast31 = 0x143;
 
-// Minimum of v over the wave, returned in every lane (uniform).
-__device__ inline uint32_t wave_min_u32(uint32_t v)
+// Wave reductions.  Each step moves the partner value with DPP and combines it; the `old`
+// operand of every move is the identity of the combining operation, which lets the compiler fold
+// the move into the ALU instruction (one v_<op>_dpp per step).  Rows of 16 lanes are reduced with
+// quad / half-row / row mirrors; rows are then combined with row_bcast:15 and row_bcast:31, after
+// which lane 63 holds the result.
+template <typename Op>
+__device__ inline uint32_t wave_reduce_u32(uint32_t v, uint32_t identity, Op op)
 {
-    v = min(v, (uint32_t)dpp<kQuadSwap1>((int)v, (int)v));
-    v = min(v, (uint32_t)dpp<kQuadSwap2>((int)v, (int)v));
-    v = min(v, (uint32_t)dpp<kRowHalfMirror>((int)v, (int)v));
-    v = min(v, (uint32_t)dpp<kRowMirror>((int)v, (int)v));
-    uint32_t a = min(readlane(v, 0), readlane(v, 16));
-    uint32_t b = min(readlane(v, 32), readlane(v, 48));
-    return min(a, b);
+    const int id = (int)identity;
+    v = op(v, (uint32_t)dpp<kQuadSwap1>(id, (int)v));
+    v = op(v, (uint32_t)dpp<kQuadSwap2>(id, (int)v));
+    v = op(v, (uint32_t)dpp<kRowHalfMirror>(id, (int)v));
+    v = op(v, (uint32_t)dpp<kRowMirror>(id, (int)v));
+    v = op(v, (uint32_t)dpp<kRowBcast15, 0xa>(id, (int)v));
+    v = op(v, (uint32_t)dpp<kRowBcast31, 0xc>(id, (int)v));
+    return readlane(v, 63);
 }
 
-__device__ inline int32_t wave_max_i32(int32_t v)
-{
-    v = max(v, dpp<kQuadSwap1>(v, v));
-    v = max(v, dpp<kQuadSwap2>(v, v));
-    v = max(v, dpp<kRowHalfMirror>(v, v));
-    v = max(v, dpp<kRowMirror>(v, v));
-    int32_t a = max(readlane_i(v, 0), readlane_i(v, 16));
-    int32_t b = max(readlane_i(v, 32), readlane_i(v, 48));
-    return max(a, b);
-}
+struct OpMinU { __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return min(a, b); } };
+struct OpOrU { __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a | b; } };
+struct OpXorU { __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a ^ b; } };
+struct OpAddU { __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a + b; } };
 
-__device__ inline int32_t wave_sum_i32(int32_t v)
-{
-    v += dpp<kQuadSwap1>(v, v);
-    v += dpp<kQuadSwap2>(v, v);
-    v += dpp<kRowHalfMirror>(v, v);
-    v += dpp<kRowMirror>(v, v);
-    return readlane_i(v, 0) + readlane_i(v, 16) + readlane_i(v, 32) + readlane_i(v, 48);
-}
+// Minimum of v over the wave (uniform result).
+__device__ inline uint32_t wave_min_u32(uint32_t v) { return wave_reduce_u32(v, 0xFFFFFFFFu, OpMinU()); }
 
-__device__ inline uint32_t wave_xor_u32(uint32_t v)
-{
-    v ^= (uint32_t)dpp<kQuadSwap1>((int)v, (int)v);
-    v ^= (uint32_t)dpp<kQuadSwap2>((int)v, (int)v);
-    v ^= (uint32_t)dpp<kRowHalfMirror>((int)v, (int)v);
-    v ^= (uint32_t)dpp<kRowMirror>((int)v, (int)v);
-    return readlane(v, 0) ^ readlane(v, 16) ^ readlane(v, 32) ^ readlane(v, 48);
-}
+// Bitwise OR of v over the wave (uniform result).
+__device__ inline uint32_t wave_or_u32(uint32_t v) { return wave_reduce_u32(v, 0u, OpOrU()); }
+
+__device__ inline int32_t wave_sum_i32(int32_t v) { return (int32_t)wave_reduce_u32((uint32_t)v, 0u, OpAddU()); }
+
+__device__ inline uint32_t wave_xor_u32(uint32_t v) { return wave_reduce_u32(v, 0u, OpXorU()); }
 
 __device__ inline uint64_t wave_xor_u64(uint64_t v)
 {
@@ -148,5 +140,14 @@ __device__ inline uint32_t funnel(uint32_t hi, uint32_t lo, int sh)
 }
 
 __device__ inline int popc(uint32_t v) { return __builtin_popcount(v); }
+
+// popcount(x) + acc as one v_bcnt_u32_b32; written as an instruction so that a run of them stays
+// a dependent chain instead of being re-associated into separate popcounts and adds.
+__device__ inline uint32_t bcnt_acc(uint32_t x, uint32_t acc)
+{
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
 
 } // namespace liblabs

@@ -1,819 +1,18 @@
-// walk_kernels.hip -- the gfx950 kernels of the skew-symmetric self-avoiding walk
-// (Section 3, Algorithm 1 of Brest & Boskovic, arXiv:2011.00068, in its self-avoiding-walk
-// reading) and of the batched one-flip evaluation.
-//
-// Mapping: one walk per 64-lane wavefront.  Lane l owns the flips j = l + 64 g (g < G flip
-// groups) and the even shifts k = 2 kappa + 2 with kappa = l + 64 q.  All walk state lives in
-// registers and a per-wave LDS block; HBM holds only the walk's visited table and its resume
-// record.  Everything is int32 / uint32 / uint64 integer arithmetic, bit-exact.
-//
-// Scoring (the one-flip evaluation, derived from Eq. (1) and (4)).  With s_i = 1 - 2 b_i, L =
-// 2c + 1, flip j < c negating s_j and s_m (m = L-1-j), and d = m - j:
-//   dC_k = -4 s_j u_jk,  u_jk = p_k + q_k - [k = d] p_k,
-//   p_k = s_{j+k} [j+k <= L-1],  q_k = s_{j-k} [j-k >= 0],
-// and for the centre j = c: u_ck = q_k.  The flipped ISL is
-//   ISL_j = sum_k (C_k + dC_k)^2 = ISL - 8 s_j G_j + 16 H_j,
-//   G_j = sum_k C_k u_jk,  H_j = sum_k u_jk^2.
-// Two variants compute it:
-//  * BITSLICE: C is held as P two's-complement bit planes (P = bits of max |C_k|, one ballot
-//    per plane) and the sequence as bit strings split by index parity; the windows
-//    Wp[kappa] = b_{j+k}, Wq[kappa] = b_{j-k} are funnel shifts of those strings, so
-//      sum_kappa C_kappa (Wp + Wq) = sum_t w_t [popc(plane_t & Wp) + popc(plane_t & Wq)],
-//    and with prefix sums of C (PSX) over the valid shifts
-//      G_j = PSX[np] + PSX[nq] - 2 sum C (Wp + Wq) - C_d s_m,
-//      H_j = np + nq + 2 R_j - 1 - 2 s_m q_d,  R_j = sum_{k <= j} s_{j+k} s_{j-k},
-//    where np / nq count the valid p / q shifts.  The centre uses G = PSX[nq] - 2 sum C Wq and
-//    H = nq.
-//  * DIRECT: the sequence as int8 in LDS (zero padded), C as int32 in LDS, and the sum of
-//    (C_k - 4 s_j u_jk)^2 accumulated term by term, with the k = d term fixed up afterwards.
+// walk_kernels.hip -- launch wrappers of the walk kernels, the batched one-flip evaluation
+// kernel and the small state kernels.  The walk itself is in walk_impl.hpp; its kernels are
+// instantiated in walk_inst_*.hip (one translation unit per variant and probe width).
 
-#include "internal.hpp"
+#include "walk_impl.hpp"
 
 namespace liblabs {
 
-// ---------------------------------------------------------------------------------------------
-// Per-wave LDS block.
-// ---------------------------------------------------------------------------------------------
-constexpr int kSeqOff = 384;   // direct variant: s_i stored at s8[kSeqOff + i]
-constexpr int kSeqBytes = 1280; // zero padding on both sides covers every j +- k
-
-struct WaveLdsBits {
-    uint32_t par[2][kParWords]; // bit a of par[p] = b_{2a+p} (0 past the sequence end)
-    uint32_t rev[2][kRevWords]; // bit a of rev[p] = bit (kNA-1-a) of par[p], 0 past kNA-1
-    uint32_t xw[kXWords];       // free bits
-    int32_t C[kCMax + 1];       // C_{2 kappa + 2} at index kappa (0 for kappa >= c)
-    int32_t psx[kCMax + 2];     // psx[a] = sum_{kappa < a} C
-};
-
-struct WaveLdsDirect : WaveLdsBits {
-    int8_t s8[kSeqBytes]; // s_i at kSeqOff + i, 0 elsewhere
-};
-
-template <bool DIRECT> struct LdsOf { using type = WaveLdsBits; };
-template <> struct LdsOf<true> { using type = WaveLdsDirect; };
-
-__device__ inline void lds_fence() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront"); __builtin_amdgcn_wave_barrier(); }
-
-// ---------------------------------------------------------------------------------------------
-// Uniform helpers on free-bit vectors held as kXWords uniform words.
-// ---------------------------------------------------------------------------------------------
-__device__ inline uint32_t xbit_uniform(const uint32_t (&x)[kXWords], int j)
-{
-    uint32_t w = 0;
-#pragma unroll
-    for (int i = 0; i < kXWords; i++)
-        w = (i == (j >> 5)) ? x[i] : w;
-    return (w >> (j & 31)) & 1u;
-}
-
-__device__ inline void xflip_uniform(uint32_t (&x)[kXWords], int j)
-{
-#pragma unroll
-    for (int i = 0; i < kXWords; i++)
-        x[i] ^= (i == (j >> 5)) ? (1u << (j & 31)) : 0u;
-}
-
-// Start state of restart r (SplitMix64 words, bit j of x = bit j%64 of word j/64, j < n).
-__device__ inline void start_bits(uint64_t seed, uint32_t walk_id, uint32_t restart, int n,
-                                  uint32_t (&x)[kXWords])
-{
-    const uint64_t kw = sm_at(seed, walk_id);
-    const uint64_t kr = sm_at(kw, restart);
-#pragma unroll
-    for (int w = 0; w < kXWords / 2; w++) {
-        uint64_t v = sm_at(kr, (uint64_t)w);
-        const int lo = 64 * w;
-        if (lo >= n)
-            v = 0;
-        else if (n - lo < 64)
-            v &= (1ull << (n - lo)) - 1ull;
-        x[2 * w] = (uint32_t)v;
-        x[2 * w + 1] = (uint32_t)(v >> 32);
-    }
-}
-
-// ---------------------------------------------------------------------------------------------
-// The walker: one wave's view of one walk.
-//   G  = flip groups (n <= 64 G), KW = 32-bit words of a shift window (c <= 32 KW).
-// ---------------------------------------------------------------------------------------------
-template <int G, int KW, bool DIRECT>
-struct Walker {
-    static constexpr int QR = (KW + 1) / 2; // lane-held C registers: kappa = lane + 64 q
-    using Lds = typename LdsOf<DIRECT>::type;
-
-    int L, c, n;
-    int lane; // lane id, laundered every step so that lane-derived values are recomputed
-    int32_t isl;
-    uint64_t h;
-    uint32_t x[kXWords];
-    int32_t Cv[QR];
-    int32_t sbit[G];
-    int planes;
-    Lds *lds;
-    const uint64_t *zk;
-
-    // b_i of the full sequence (Eq. (4) mirror for i > c), read from the LDS copy of x.
-    __device__ inline uint32_t seq_bit(int i) const
-    {
-        if (i < 0 || i >= L)
-            return 0u;
-        const int f = (i <= c) ? i : 2 * c - i;
-        const uint32_t b = (lds->xw[f >> 5] >> (f & 31)) & 1u;
-        return (i <= c) ? b : (b ^ (uint32_t)((i - c) & 1));
-    }
-
-    // Rebuild everything derived from x: bit strings, C_k from scratch (Eq. (1)), ISL (Eq. (2)),
-    // Zobrist hash.
-    __device__ __forceinline__ void rebuild()
-    {
-        const int lane = this->lane;
-        if (lane == 0) {
-#pragma unroll
-            for (int w = 0; w < kXWords; w++)
-                lds->xw[w] = x[w];
-        }
-        lds_fence();
-        // parity strings and their reversals, 64 bit positions per ballot
-#pragma unroll
-        for (int r = 0; r < 3; r++) {
-            const int a = lane + 64 * r;
-            const int ar = kNA - 1 - a;
-#pragma unroll
-            for (int p = 0; p < 2; p++) {
-                const uint64_t m = ballot(seq_bit(2 * a + p) != 0u);
-                const uint64_t mr = ballot(seq_bit(2 * ar + p) != 0u);
-                if (lane == 0) {
-                    lds->par[p][2 * r] = (uint32_t)m;
-                    lds->par[p][2 * r + 1] = (uint32_t)(m >> 32);
-                    lds->rev[p][2 * r] = (uint32_t)mr;
-                    lds->rev[p][2 * r + 1] = (uint32_t)(mr >> 32);
-                }
-            }
-        }
-        if (lane < 2 * (kParWords - 6)) {
-            lds->par[lane & 1][6 + (lane >> 1)] = 0u;
-        }
-        if (lane < 2 * (kRevWords - 6)) {
-            lds->rev[lane & 1][6 + (lane >> 1)] = 0u;
-        }
-        if constexpr (DIRECT) {
-            for (int i = lane; i < kSeqBytes; i += kWave) {
-                const int pos = i - kSeqOff;
-                lds->s8[i] = (pos >= 0 && pos < L) ? (int8_t)(1 - 2 * (int)seq_bit(pos)) : (int8_t)0;
-            }
-        }
-        lds_fence();
-        // per-lane free bits of the owned flips
-#pragma unroll
-        for (int g = 0; g < G; g++) {
-            const int j = lane + 64 * g;
-            sbit[g] = (j <= c) ? (int32_t)seq_bit(j) : 0;
-        }
-        // C_k for even k from the parity strings: pairs (i, i+k) share the parity of i, and
-        // s_i s_{i+k} = 1 - 2 (b_i xor b_{i+k}).
-        int32_t sq = 0;
-#pragma unroll
-        for (int q = 0; q < QR; q++) {
-            const int kappa = lane + 64 * q;
-            int32_t Ck = 0;
-            if (kappa < c) {
-                const int k = 2 * kappa + 2;
-                const int sh = kappa + 1;
-#pragma unroll
-                for (int p = 0; p < 2; p++) {
-                    const int last = L - 1 - k - p; // largest 2a with 2a + p + k <= L-1
-                    const int cnt = last >= 0 ? last / 2 + 1 : 0;
-                    int diff = 0;
-                    for (int w = 0; 32 * w < cnt; w++) {
-                        const uint32_t base = lds->par[p][w];
-                        const uint32_t shifted =
-                            funnel(lds->par[p][(sh >> 5) + w + 1], lds->par[p][(sh >> 5) + w], sh & 31);
-                        diff += popc((base ^ shifted) & low_mask(cnt - 32 * w));
-                    }
-                    Ck += cnt - 2 * diff;
-                }
-            }
-            Cv[q] = Ck;
-            sq += Ck * Ck;
-        }
-        isl = wave_sum_i32(sq);
-        uint64_t hz = 0;
-#pragma unroll
-        for (int g = 0; g < G; g++) {
-            const int j = lane + 64 * g;
-            if (j <= c && sbit[g])
-                hz ^= zk[j];
-        }
-        h = wave_xor_u64(hz);
-    }
-
-    // Per-step preparation: C to LDS, prefix sums, number of bit planes.
-    __device__ __forceinline__ void prepare()
-    {
-        const int lane = this->lane;
-        int32_t running = 0;
-        int32_t mag = 0;
-#pragma unroll
-        for (int q = 0; q < QR; q++) {
-            const int kappa = lane + 64 * q;
-            lds->C[kappa] = Cv[q];
-            const int32_t inc = wave_inclusive_scan(Cv[q]) + running;
-            lds->psx[kappa + 1] = inc;
-            running = readlane_i(inc, 63);
-            mag = max(mag, Cv[q] >= 0 ? Cv[q] : ~Cv[q]);
-        }
-        if (lane == 0)
-            lds->psx[0] = 0;
-        mag = wave_max_i32(mag);
-        planes = (mag == 0) ? 1 : 33 - __builtin_clz((uint32_t)mag);
-        lds_fence();
-    }
-
-    // Score every owned flip: isl_j[g] = ISL after flip j = lane + 64 g (garbage for j > c).
-    __device__ __forceinline__ void score(int32_t (&isl_j)[G])
-    {
-        const int lane = this->lane;
-        if constexpr (!DIRECT) {
-            uint32_t wp[G][KW];
-            uint32_t wq[G][G];
-#pragma unroll
-            for (int g = 0; g < G; g++) {
-                const int j = lane + 64 * g;
-                const int p = j & 1;
-                const int hj = j >> 1;
-                const int sp = hj + 1;
-                const uint32_t *P = lds->par[p];
-                uint32_t lo = P[sp >> 5];
-#pragma unroll
-                for (int w = 0; w < KW - g; w++) {
-                    const uint32_t hi = P[(sp >> 5) + w + 1];
-                    wp[g][w] = (j == c) ? 0u : funnel(hi, lo, sp & 31);
-                    lo = hi;
-                }
-                const int sq = kNA - hj;
-                const uint32_t *R = lds->rev[p];
-                lo = R[sq >> 5];
-#pragma unroll
-                for (int w = 0; w <= g; w++) {
-                    const uint32_t hi = R[(sq >> 5) + w + 1];
-                    wq[g][w] = funnel(hi, lo, sq & 31);
-                    lo = hi;
-                }
-            }
-            // bit-plane sums, most significant (sign) plane first
-            int32_t acc[G];
-            {
-                const int t = planes - 1;
-                uint32_t pl[KW];
-#pragma unroll
-                for (int q = 0; q < QR; q++) {
-                    const uint64_t m = ballot(((Cv[q] >> t) & 1) != 0);
-                    pl[2 * q] = (uint32_t)m;
-                    if (2 * q + 1 < KW)
-                        pl[2 * q + 1] = (uint32_t)(m >> 32);
-                }
-#pragma unroll
-                for (int g = 0; g < G; g++) {
-                    int tmp = 0;
-#pragma unroll
-                    for (int w = 0; w < KW - g; w++)
-                        tmp += popc(pl[w] & wp[g][w]);
-#pragma unroll
-                    for (int w = 0; w <= g; w++)
-                        tmp += popc(pl[w] & wq[g][w]);
-                    acc[g] = -tmp;
-                }
-            }
-            for (int t = planes - 2; t >= 0; t--) {
-                uint32_t pl[KW];
-#pragma unroll
-                for (int q = 0; q < QR; q++) {
-                    const uint64_t m = ballot(((Cv[q] >> t) & 1) != 0);
-                    pl[2 * q] = (uint32_t)m;
-                    if (2 * q + 1 < KW)
-                        pl[2 * q + 1] = (uint32_t)(m >> 32);
-                }
-#pragma unroll
-                for (int g = 0; g < G; g++) {
-                    int tmp = 0;
-#pragma unroll
-                    for (int w = 0; w < KW - g; w++)
-                        tmp += popc(pl[w] & wp[g][w]);
-#pragma unroll
-                    for (int w = 0; w <= g; w++)
-                        tmp += popc(pl[w] & wq[g][w]);
-                    acc[g] = 2 * acc[g] + tmp;
-                }
-            }
-            // assemble ISL_j
-#pragma unroll
-            for (int g = 0; g < G; g++) {
-                const int j = lane + 64 * g;
-                const int jc = min(j, c);
-                const int nq = jc >> 1;
-                const int np = (jc == c) ? 0 : c - ((jc + 1) >> 1);
-                int32_t Gj = lds->psx[np] + lds->psx[nq] - 2 * acc[g];
-                // R_j = sum over shifts valid on both sides of s_{j+k} s_{j-k}
-                int rc = 0;
-#pragma unroll
-                for (int w = 0; w <= g && w < KW - g; w++)
-                    rc += popc((wp[g][w] ^ wq[g][w]) & low_mask(nq - 32 * w));
-                const int32_t Rj = nq - 2 * rc;
-                int32_t Hj;
-                if (jc < c) {
-                    const int kd = c - 1 - jc;
-                    const int32_t Cd = lds->C[kd];
-                    const int32_t sm = 1 - 2 * (sbit[g] ^ ((c - jc) & 1));
-                    int32_t qd = 0;
-                    const int iq = 3 * jc - 2 * c; // index j - d of the far partner
-                    if (iq >= 0) {
-                        const int a = iq >> 1;
-                        qd = 1 - 2 * (int32_t)((lds->par[jc & 1][a >> 5] >> (a & 31)) & 1u);
-                    }
-                    Gj -= Cd * sm;
-                    Hj = np + nq + 2 * Rj - 1 - 2 * sm * qd;
-                } else {
-                    Hj = nq;
-                }
-                const int32_t sj = 1 - 2 * sbit[g];
-                isl_j[g] = isl - 8 * sj * Gj + 16 * Hj;
-            }
-        } else {
-            // direct sum of squares over the even shifts
-            const int8_t *s8 = lds->s8;
-#pragma unroll
-            for (int g = 0; g < G; g++) {
-                const int j = lane + 64 * g;
-                const int jc = min(j, c);
-                const int32_t sj4 = 4 * (1 - 2 * sbit[g]);
-                const int pbase = (jc == c) ? kSeqOff + L : kSeqOff + jc; // centre: p_k = 0
-                const int qbase = kSeqOff + jc;
-                int32_t acc = 0;
-                for (int kappa = 0; kappa < c; kappa++) {
-                    const int k = 2 * kappa + 2;
-                    const int32_t u = (int32_t)s8[pbase + k] + (int32_t)s8[qbase - k];
-                    const int32_t tt = lds->C[kappa] - sj4 * u;
-                    acc += tt * tt;
-                }
-                if (jc < c) {
-                    const int kd = c - 1 - jc;
-                    const int d = 2 * kd + 2;
-                    const int32_t qd = s8[qbase - d];
-                    const int32_t wrong = lds->C[kd] - sj4 * ((int32_t)s8[pbase + d] + qd);
-                    const int32_t right = lds->C[kd] - sj4 * qd;
-                    acc += right * right - wrong * wrong;
-                }
-                isl_j[g] = acc;
-            }
-        }
-    }
-
-    // Commit flip js (uniform): update C_k by dC_k, the bit strings / sequence, x and the hash.
-    __device__ __forceinline__ void commit(int js, int32_t isl_new)
-    {
-        const int lane = this->lane;
-        const int32_t sjs = 1 - 2 * (int32_t)xbit_uniform(x, js);
-        const int hjs = js >> 1;
-        const int pis = js & 1;
-        const int nps = (js == c) ? 0 : c - ((js + 1) >> 1);
-        const int kds = (js == c) ? -1 : c - 1 - js;
-#pragma unroll
-        for (int q = 0; q < QR; q++) {
-            const int kappa = lane + 64 * q;
-            if (kappa < c) {
-                int32_t pv = 0, qv = 0;
-                if constexpr (!DIRECT) {
-                    const int ip = hjs + 1 + kappa;
-                    const uint32_t bp = (lds->par[pis][ip >> 5] >> (ip & 31)) & 1u;
-                    pv = (kappa < nps && kappa != kds) ? 1 - 2 * (int32_t)bp : 0;
-                    const int iq = hjs - 1 - kappa;
-                    if (iq >= 0)
-                        qv = 1 - 2 * (int32_t)((lds->par[pis][iq >> 5] >> (iq & 31)) & 1u);
-                } else {
-                    const int k = 2 * kappa + 2;
-                    pv = (js == c || kappa == kds) ? 0 : (int32_t)lds->s8[kSeqOff + js + k];
-                    qv = (int32_t)lds->s8[kSeqOff + js - k];
-                }
-                Cv[q] += -4 * sjs * (pv + qv);
-            }
-        }
-        lds_fence();
-        if constexpr (!DIRECT) {
-            if (lane < 2 && (lane == 0 || js != c)) {
-                const int a = (lane == 0) ? hjs : nps; // mirror m = 2c - js has a = nps
-                atomicXor(&lds->par[pis][a >> 5], 1u << (a & 31));
-                const int ar = kNA - 1 - a;
-                atomicXor(&lds->rev[pis][ar >> 5], 1u << (ar & 31));
-            }
-        } else {
-            if (lane < 2 && (lane == 0 || js != c)) {
-                const int pos = (lane == 0) ? js : 2 * c - js;
-                lds->s8[kSeqOff + pos] = (int8_t)(-lds->s8[kSeqOff + pos]);
-            }
-        }
-        lds_fence();
-#pragma unroll
-        for (int g = 0; g < G; g++)
-            sbit[g] ^= (lane + 64 * g == js) ? 1 : 0;
-        xflip_uniform(x, js);
-        h ^= zk[js];
-        isl = isl_new;
-    }
-};
-
-// ---------------------------------------------------------------------------------------------
-// Visited table access.  Probes are issued by a subset of lanes (divergent), so they are
-// vector loads; stores are plain vector stores.
-// ---------------------------------------------------------------------------------------------
-__device__ inline void clear_table(uint64_t *T, int log2)
-{
-    const int lane = lane_id();
-    uint4 *T4 = reinterpret_cast<uint4 *>(T);
-    const int64_t n4 = (int64_t)1 << (log2 - 1);
-    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
-    for (int64_t i = lane; i < n4; i += kWave)
-        T4[i] = z;
-}
-
-__device__ inline uint64_t slot_of(uint64_t hh, uint32_t x0, bool exact, int log2)
-{
-    return exact ? (uint64_t)x0 : (hh >> (64 - log2));
-}
-
-// ---------------------------------------------------------------------------------------------
-// One walk, advanced until its budget, its target, or the launch's step limit.
-// ---------------------------------------------------------------------------------------------
-template <int G, int KW, bool DIRECT, int PW>
-__device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *__restrict__ tables,
-                         int32_t *__restrict__ trace, int32_t *__restrict__ scores, int64_t chunk,
-                         typename LdsOf<DIRECT>::type *lds, const uint64_t *zk)
-{
-    using W = Walker<G, KW, DIRECT>;
-    int lane = lane_id();
-    asm volatile("" : "+v"(lane)); // nothing lane-derived is hoisted out of the walk
-    WalkState &ws = *wsp;
-
-    const int32_t status0 = ws.status;
-    if (status0 == kDone)
-        return;
-
-    W w;
-    w.lane = lane;
-    w.L = ws.L;
-    w.c = (w.L - 1) / 2;
-    w.n = w.c + 1;
-    w.lds = lds;
-    w.zk = zk;
-    const int L = w.L, n = w.n;
-    const int tlog2 = ws.table_log2;
-    const bool exact = n <= tlog2;
-    const uint64_t seed = ws.seed;
-    const uint32_t walk_id = ws.walk_id;
-    const int64_t steps = ws.steps;
-    const int64_t R = ws.restart_period;
-    const int64_t target = ws.target_isl;
-    const int64_t watch = ws.watch_isl;
-    uint64_t *T = tables + ws.table_offset;
-    const int64_t trace_off = ws.trace_offset;
-    const int64_t score_off = ws.score_offset;
-
-    int64_t t, flips, hit, wstep, best_isl, best_step;
-    int32_t restart_idx, restarts, traps;
-    uint32_t best_x[kXWords];
-
-    if (status0 == kFresh) {
-        restart_idx = 0;
-        start_bits(seed, walk_id, 0u, n, w.x);
-        clear_table(T, tlog2);
-        w.rebuild();
-        if (lane == 0)
-            T[slot_of(w.h, w.x[0], exact, tlog2)] = w.h | 1ull;
-        t = 0;
-        flips = 0;
-        restarts = 0;
-        traps = 0;
-        best_isl = w.isl;
-        best_step = 0;
-#pragma unroll
-        for (int i = 0; i < kXWords; i++)
-            best_x[i] = w.x[i];
-        hit = (target >= 0 && w.isl <= target) ? 0 : -1;
-        wstep = (watch >= 0 && w.isl <= watch) ? 0 : -1;
-    } else {
-#pragma unroll
-        for (int i = 0; i < kXWords; i++) {
-            w.x[i] = ws.x[i];
-            best_x[i] = ws.best_x[i];
-        }
-        restart_idx = ws.restart_idx;
-        restarts = ws.restarts;
-        traps = ws.traps;
-        t = ws.t;
-        flips = ws.flips;
-        hit = ws.hit_step;
-        wstep = ws.watch_step;
-        best_isl = ws.best_isl;
-        best_step = ws.best_step;
-        w.rebuild();
-    }
-
-    // next step index at which a periodic restart is due (a multiple of R); one division per
-    // launch instead of a 64-bit remainder per step
-    int64_t next_restart = (R > 0) ? (t / R + 1) * R : INT64_MAX;
-    int64_t t_end = steps;
-    if (chunk > 0 && t + chunk < t_end)
-        t_end = t + chunk;
-    if (ws.step_cap < t_end)
-        t_end = ws.step_cap;
-
-    while (t < t_end && !(target >= 0 && hit >= 0)) {
-        // Keep per-lane index arithmetic inside the loop instead of pinning ~100 VGPRs of
-        // loop invariants for the whole walk: the values are cheap to recompute and the
-        // registers are worth more as occupancy.
-        asm volatile("" : "+v"(w.lane));
-        w.prepare();
-        int32_t isl_j[G];
-        w.score(isl_j);
-        uint32_t keys[G];
-#pragma unroll
-        for (int g = 0; g < G; g++) {
-            const int j = w.lane + 64 * g;
-            keys[g] = (j < n) ? (((uint32_t)isl_j[g] << 8) | (uint32_t)j) : 0xFFFFFFFFu;
-            if (score_off >= 0 && j < n)
-                scores[score_off + t * n + j] = isl_j[g];
-        }
-        flips += n;
-
-        // best non-visited flip: take the PW smallest keys, probe them together
-        int js = -1;
-        int32_t isl_new = 0;
-        while (true) {
-            uint32_t cand[PW];
-#pragma unroll
-            for (int i = 0; i < PW; i++) {
-                uint32_t km = keys[0];
-#pragma unroll
-                for (int g = 1; g < G; g++)
-                    km = min(km, keys[g]);
-                cand[i] = wave_min_u32(km);
-                if (cand[i] != 0xFFFFFFFFu) {
-#pragma unroll
-                    for (int g = 0; g < G; g++)
-                        keys[g] = (w.lane + 64 * g == (int)(cand[i] & 255u)) ? 0xFFFFFFFFu : keys[g];
-                }
-            }
-            if (cand[0] == 0xFFFFFFFFu)
-                break; // every flip leads to a visited state
-            // w.lane i probes candidate i
-            uint32_t my = cand[0];
-#pragma unroll
-            for (int i = 1; i < PW; i++)
-                my = (w.lane == i) ? cand[i] : my;
-            const int jm = min((int)(my & 255u), n - 1);
-            const uint64_t hc = w.h ^ zk[jm];
-            uint32_t x0 = w.x[0] ^ (1u << (jm & 31));
-            if (jm >= 32)
-                x0 = w.x[0];
-            uint64_t got = 0;
-            if (w.lane < PW && my != 0xFFFFFFFFu)
-                got = T[slot_of(hc, x0, exact, tlog2)];
-            const bool fresh = (w.lane < PW) && (my != 0xFFFFFFFFu) && (got != (hc | 1ull));
-            const uint64_t okmask = ballot(fresh);
-            if (okmask != 0ull) {
-                const int first = __builtin_ctzll(okmask);
-                uint32_t pick = cand[0];
-#pragma unroll
-                for (int i = 1; i < PW; i++)
-                    pick = (first == i) ? cand[i] : pick;
-                js = (int)(pick & 255u);
-                isl_new = (int32_t)(pick >> 8);
-                break;
-            }
-            if (cand[PW - 1] == 0xFFFFFFFFu)
-                break;
-        }
-
-        if (js < 0) {
-            // trapped: restart from the next start state; the step counts
-            traps++;
-            restarts++;
-            restart_idx++;
-            start_bits(seed, walk_id, (uint32_t)restart_idx, n, w.x);
-            clear_table(T, tlog2);
-            w.rebuild();
-            if (w.lane == 0)
-                T[slot_of(w.h, w.x[0], exact, tlog2)] = w.h | 1ull;
-            t++;
-            if (t == next_restart)
-                next_restart += R; // a trap restart replaces a periodic one due at this step
-            if (trace_off >= 0 && w.lane == 0) {
-                trace[2 * (trace_off + t - 1)] = -1;
-                trace[2 * (trace_off + t - 1) + 1] = w.isl;
-            }
-            continue;
-        }
-
-        w.commit(js, isl_new);
-        if (w.lane == 0)
-            T[slot_of(w.h, w.x[0], exact, tlog2)] = w.h | 1ull;
-        t++;
-        if (trace_off >= 0 && w.lane == 0) {
-            trace[2 * (trace_off + t - 1)] = js;
-            trace[2 * (trace_off + t - 1) + 1] = w.isl;
-        }
-        if (w.isl < best_isl) {
-            best_isl = w.isl;
-            best_step = t;
-#pragma unroll
-            for (int i = 0; i < kXWords; i++)
-                best_x[i] = w.x[i];
-        }
-        if (target >= 0 && hit < 0 && w.isl <= target)
-            hit = t;
-        if (watch >= 0 && wstep < 0 && w.isl <= watch)
-            wstep = t;
-        bool period_due = false;
-        if (t == next_restart) {
-            period_due = true;
-            next_restart += R;
-        }
-        if (period_due && t < steps && !(target >= 0 && hit >= 0)) {
-            restarts++;
-            restart_idx++;
-            start_bits(seed, walk_id, (uint32_t)restart_idx, n, w.x);
-            clear_table(T, tlog2);
-            w.rebuild();
-            if (w.lane == 0)
-                T[slot_of(w.h, w.x[0], exact, tlog2)] = w.h | 1ull;
-        }
-    }
-
-    if (lane == 0) {
-        ws.t = t;
-        ws.flips = flips;
-        ws.hit_step = hit;
-        ws.watch_step = wstep;
-        ws.best_isl = best_isl;
-        ws.best_step = best_step;
-        ws.h = w.h;
-        ws.isl = w.isl;
-        ws.restart_idx = restart_idx;
-        ws.restarts = restarts;
-        ws.traps = traps;
-#pragma unroll
-        for (int i = 0; i < kXWords; i++) {
-            ws.x[i] = w.x[i];
-            ws.best_x[i] = best_x[i];
-        }
-        ws.status = (t >= steps || (target >= 0 && hit >= 0)) ? kDone : kRunning;
-    }
-    (void)L;
-}
-
-// ---------------------------------------------------------------------------------------------
-// Shapes.
-// ---------------------------------------------------------------------------------------------
-//  shape : (G, KW)   lengths
-//    0   : (1, 1)    c <= 32
-//    1   : (1, 2)    33 <= c <= 63
-//    2   : (2, 2)    c == 64
-//    3   : (2, 3)    65 <= c <= 96
-//    4   : (2, 4)    97 <= c <= 127
-//    5   : (3, 4)    c == 128
-//    6   : (3, 5)    129 <= c <= 160
-//    7   : (3, 6)    161 <= c <= 191
-__host__ __device__ int shape_for_length_dev(int L)
-{
-    const int c = (L - 1) / 2;
-    if (c <= 32) return 0;
-    if (c <= 63) return 1;
-    if (c == 64) return 2;
-    if (c <= 96) return 3;
-    if (c <= 127) return 4;
-    if (c == 128) return 5;
-    if (c <= 160) return 6;
-    return 7;
-}
-
 int shape_for_length(int L) { return shape_for_length_dev(L); }
+
 
 int shape_groups(int shape)
 {
     static const int g[8] = {1, 1, 2, 2, 2, 3, 3, 3};
     return g[shape & 7];
-}
-
-template <int SHAPE> struct ShapeGK;
-template <> struct ShapeGK<0> { static constexpr int G = 1, KW = 1; };
-template <> struct ShapeGK<1> { static constexpr int G = 1, KW = 2; };
-template <> struct ShapeGK<2> { static constexpr int G = 2, KW = 2; };
-template <> struct ShapeGK<3> { static constexpr int G = 2, KW = 3; };
-template <> struct ShapeGK<4> { static constexpr int G = 2, KW = 4; };
-template <> struct ShapeGK<5> { static constexpr int G = 3, KW = 4; };
-template <> struct ShapeGK<6> { static constexpr int G = 3, KW = 5; };
-template <> struct ShapeGK<7> { static constexpr int G = 3, KW = 6; };
-
-// ---------------------------------------------------------------------------------------------
-// Kernels.
-// ---------------------------------------------------------------------------------------------
-__device__ inline void fill_zobrist(uint64_t *zk)
-{
-    for (int j = threadIdx.x; j < kNMax; j += blockDim.x)
-        zk[j] = zobrist_key(j);
-    __syncthreads();
-}
-
-// SHAPE >= 0: every walk has that shape.  SHAPE < 0: any shape, dispatched per walk.
-template <int SHAPE, bool DIRECT, int PW>
-__device__ __forceinline__ void run_any(WalkState *ws, uint64_t *tables, int32_t *trace, int32_t *scores,
-                               int64_t chunk, typename LdsOf<DIRECT>::type *lds, const uint64_t *zk)
-{
-    if constexpr (SHAPE >= 0) {
-        run_walk<ShapeGK<SHAPE>::G, ShapeGK<SHAPE>::KW, DIRECT, PW>(ws, tables, trace, scores, chunk, lds, zk);
-    } else {
-        switch (shape_for_length_dev(ws->L)) {
-        case 0: run_walk<1, 1, DIRECT, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
-        case 1: run_walk<1, 2, DIRECT, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
-        case 2: run_walk<2, 2, DIRECT, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
-        case 3: run_walk<2, 3, DIRECT, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
-        case 4: run_walk<2, 4, DIRECT, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
-        case 5: run_walk<3, 4, DIRECT, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
-        case 6: run_walk<3, 5, DIRECT, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
-        default: run_walk<3, 6, DIRECT, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
-        }
-    }
-}
-
-constexpr int kMaxWavesPerBlock = 8;
-
-template <int SHAPE, bool DIRECT, int PW>
-__global__ void __launch_bounds__(64 * kMaxWavesPerBlock) k_walk(WalkState *__restrict__ states, int32_t n_walks,
-                                              const int32_t *__restrict__ order,
-                                              uint64_t *__restrict__ tables, int32_t *__restrict__ trace,
-                                              int32_t *__restrict__ scores, int64_t chunk,
-                                              int32_t *__restrict__ counter)
-{
-    using Lds = typename LdsOf<DIRECT>::type;
-    __shared__ uint64_t zk[kNMax];
-    extern __shared__ __align__(16) unsigned char dyn_smem[];
-    fill_zobrist(zk);
-    const int wave = (int)(threadIdx.x >> 6);
-    const int wpb = (int)(blockDim.x >> 6);
-    Lds *lds = reinterpret_cast<Lds *>(dyn_smem) + wave;
-    // one walk per wave (counter == nullptr), or the persistent form: every wave pulls walks
-    // from the counter until the list is exhausted
-    int idx = (int)blockIdx.x * wpb + wave;
-    bool first = true;
-    while (true) {
-        if (counter != nullptr) {
-            int got = 0;
-            if (lane_id() == 0)
-                got = atomicAdd(counter, 1);
-            idx = __builtin_amdgcn_readlane(got, 0);
-        } else if (!first) {
-            break;
-        }
-        first = false;
-        if (idx >= n_walks)
-            break;
-        const int wi = order ? order[idx] : idx;
-        run_any<SHAPE, DIRECT, PW>(&states[wi], tables, trace, scores, chunk, lds, zk);
-    }
-}
-
-template <int SHAPE, bool DIRECT>
-__global__ void __launch_bounds__(64) k_flip_scores(int L, int count, const uint32_t *__restrict__ xs,
-                                                    int32_t *__restrict__ out)
-{
-    using Lds = typename LdsOf<DIRECT>::type;
-    constexpr int G = ShapeGK<SHAPE>::G, KW = ShapeGK<SHAPE>::KW;
-    __shared__ uint64_t zk[kNMax];
-    __shared__ Lds lds;
-    fill_zobrist(zk);
-    const int r = (int)blockIdx.x;
-    if (r >= count)
-        return;
-    Walker<G, KW, DIRECT> w;
-    w.lane = lane_id();
-    w.L = L;
-    w.c = (L - 1) / 2;
-    w.n = w.c + 1;
-    w.lds = &lds;
-    w.zk = zk;
-#pragma unroll
-    for (int i = 0; i < kXWords; i++)
-        w.x[i] = xs[(int64_t)r * kXWords + i];
-    w.rebuild();
-    w.prepare();
-    int32_t isl_j[G];
-    w.score(isl_j);
-    const int lane = lane_id();
-#pragma unroll
-    for (int g = 0; g < G; g++) {
-        const int j = lane + 64 * g;
-        if (j < w.n)
-            out[(int64_t)r * w.n + j] = isl_j[g];
-    }
 }
 
 __global__ void k_reset(WalkState *__restrict__ states, const WalkState *__restrict__ pristine,
@@ -829,40 +28,16 @@ __global__ void k_reset(WalkState *__restrict__ states, const WalkState *__restr
 // ---------------------------------------------------------------------------------------------
 // Launch wrappers.
 // ---------------------------------------------------------------------------------------------
-using WalkKernel = void (*)(WalkState *, int32_t, const int32_t *, uint64_t *, int32_t *, int32_t *,
-                            int64_t, int32_t *);
-
-template <int SHAPE, bool DIRECT>
-static WalkKernel pick_pw(int pw)
-{
-    if (pw >= 4) return k_walk<SHAPE, DIRECT, 4>;
-    if (pw == 2 || pw == 3) return k_walk<SHAPE, DIRECT, 2>;
-    return k_walk<SHAPE, DIRECT, 1>;
-}
-
-template <bool DIRECT>
-static WalkKernel pick_shape(int shape, int pw)
-{
-    switch (shape) {
-    case 0: return pick_pw<0, DIRECT>(pw);
-    case 1: return pick_pw<1, DIRECT>(pw);
-    case 2: return pick_pw<2, DIRECT>(pw);
-    case 3: return pick_pw<3, DIRECT>(pw);
-    case 4: return pick_pw<4, DIRECT>(pw);
-    case 5: return pick_pw<5, DIRECT>(pw);
-    case 6: return pick_pw<6, DIRECT>(pw);
-    case 7: return pick_pw<7, DIRECT>(pw);
-    default: return pick_pw<-1, DIRECT>(pw);
-    }
-}
 
 hipError_t launch_walk(const WalkLaunch &lp, WalkState *states, int32_t n_walks, const int32_t *order,
                        uint64_t *tables, int32_t *trace, int32_t *scores, int32_t *counter,
                        hipStream_t stream)
 {
     const bool direct = lp.variant == LABS_VARIANT_DIRECT;
-    WalkKernel k = direct ? pick_shape<true>(lp.shape, lp.probe_width)
-                          : pick_shape<false>(lp.shape, lp.probe_width);
+    WalkKernel k = direct ? (lp.probe_width >= 2 ? pick_walk_kernel_direct_pw2(lp.shape)
+                                                 : pick_walk_kernel_direct_pw1(lp.shape))
+                          : (lp.probe_width >= 2 ? pick_walk_kernel_bits_pw2(lp.shape)
+                                                 : pick_walk_kernel_bits_pw1(lp.shape));
     const int wpb = lp.waves_per_block;
     if (wpb < 1 || wpb > kMaxWavesPerBlock)
         return hipErrorInvalidConfiguration; // the kernel is compiled for at most 8 waves per block
