@@ -57,6 +57,16 @@ __device__ inline uint32_t uniform(uint32_t v) { return (uint32_t)__builtin_amdg
 
 __device__ inline uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+// A wave-uniform value read from memory, moved to scalar registers so that the arithmetic that
+// follows runs on the scalar unit (a vector load leaves even a uniform value in VGPRs).
+__device__ inline uint32_t su(uint32_t v) { return uniform(v); }
+__device__ inline int32_t su(int32_t v) { return (int32_t)uniform((uint32_t)v); }
+__device__ inline uint64_t su(uint64_t v)
+{
+    return ((uint64_t)uniform((uint32_t)(v >> 32)) << 32) | uniform((uint32_t)v);
+}
+__device__ inline int64_t su(int64_t v) { return (int64_t)su((uint64_t)v); }
+
 // DPP move of src into the lane layout given by CTRL (rows of 16 lanes); lanes whose source is
 // outside the row (or disabled by the masks) get `old`.
 template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf>

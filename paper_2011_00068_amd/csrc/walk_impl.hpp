@@ -89,8 +89,9 @@ __device__ inline void start_bits(uint64_t seed, uint32_t walk_id, uint32_t rest
             v = 0;
         else if (n - lo < 64)
             v &= (1ull << (n - lo)) - 1ull;
-        x[2 * w] = (uint32_t)v;
-        x[2 * w + 1] = (uint32_t)(v >> 32);
+        // the words are wave-uniform; keep them in scalar registers
+        x[2 * w] = uniform((uint32_t)v);
+        x[2 * w + 1] = uniform((uint32_t)(v >> 32));
     }
 }
 
@@ -417,7 +418,8 @@ struct Walker {
         for (int g = 0; g < G; g++)
             sbit[g] ^= (lane + 64 * g == js) ? 1 : 0;
         xflip_uniform(x, js);
-        h ^= zk[js];
+        const uint64_t z = zk[js];
+        h ^= ((uint64_t)uniform((uint32_t)(z >> 32)) << 32) | uniform((uint32_t)z);
         isl = isl_new;
     }
 };
@@ -457,29 +459,29 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
     asm volatile("" : "+v"(lane)); // nothing lane-derived is hoisted out of the walk
     WalkState &ws = *wsp;
 
-    const int32_t status0 = ws.status;
+    const int32_t status0 = su(ws.status);
     if (status0 == kDone)
         return;
 
     W w;
     w.lane = lane;
-    w.L = ws.L;
+    w.L = su(ws.L);
     w.c = (w.L - 1) / 2;
     w.n = w.c + 1;
     w.lds = lds;
     w.zk = zk;
     const int L = w.L, n = w.n;
-    const int tlog2 = ws.table_log2;
+    const int tlog2 = su(ws.table_log2);
     const bool exact = n <= tlog2;
-    const uint64_t seed = ws.seed;
-    const uint32_t walk_id = ws.walk_id;
-    const int64_t steps = ws.steps;
-    const int64_t R = ws.restart_period;
-    const int64_t target = ws.target_isl;
-    const int64_t watch = ws.watch_isl;
-    uint64_t *T = tables + ws.table_offset;
-    const int64_t trace_off = ws.trace_offset;
-    const int64_t score_off = ws.score_offset;
+    const uint64_t seed = su(ws.seed);
+    const uint32_t walk_id = su(ws.walk_id);
+    const int64_t steps = su(ws.steps);
+    const int64_t R = su(ws.restart_period);
+    const int64_t target = su(ws.target_isl);
+    const int64_t watch = su(ws.watch_isl);
+    uint64_t *T = tables + su(ws.table_offset);
+    const int64_t trace_off = su(ws.trace_offset);
+    const int64_t score_off = su(ws.score_offset);
 
     int64_t t, flips, hit, wstep, best_isl, best_step;
     int32_t restart_idx, restarts, traps;
@@ -506,18 +508,18 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
     } else {
 #pragma unroll
         for (int i = 0; i < kXWords; i++) {
-            w.x[i] = ws.x[i];
-            best_x[i] = ws.best_x[i];
+            w.x[i] = su(ws.x[i]);
+            best_x[i] = su(ws.best_x[i]);
         }
-        restart_idx = ws.restart_idx;
-        restarts = ws.restarts;
-        traps = ws.traps;
-        t = ws.t;
-        flips = ws.flips;
-        hit = ws.hit_step;
-        wstep = ws.watch_step;
-        best_isl = ws.best_isl;
-        best_step = ws.best_step;
+        restart_idx = su(ws.restart_idx);
+        restarts = su(ws.restarts);
+        traps = su(ws.traps);
+        t = su(ws.t);
+        flips = su(ws.flips);
+        hit = su(ws.hit_step);
+        wstep = su(ws.watch_step);
+        best_isl = su(ws.best_isl);
+        best_step = su(ws.best_step);
         w.rebuild();
     }
 
@@ -528,8 +530,9 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
     int64_t t_end = steps;
     if (chunk > 0 && t + chunk < t_end)
         t_end = t + chunk;
-    if (ws.step_cap < t_end)
-        t_end = ws.step_cap;
+    const int64_t cap = su(ws.step_cap);
+    if (cap < t_end)
+        t_end = cap;
     const int32_t nsteps = (int32_t)max<int64_t>(0, min<int64_t>(t_end - t0, (int64_t)kMaxStepsPerLaunch));
     const int32_t tgt = target < 0 ? -1 : (int32_t)min<int64_t>(target, INT32_MAX);
     const int32_t wch = watch < 0 ? -1 : (int32_t)min<int64_t>(watch, INT32_MAX);
@@ -539,134 +542,165 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
     bool watch_found = wstep >= 0;
     bool stop = tgt >= 0 && hit_found;
     int32_t best32 = (int32_t)best_isl;
+    // steps of this launch at which best / hit / watch were reached (-1 = not in this launch)
+    int32_t best_ts = -1, hit_ts = -1, watch_ts = -1;
+    // steps left before the budget, as seen from this launch (periodic restarts stop there)
+    const int32_t left32 = (int32_t)min<int64_t>(steps - t0, INT32_MAX);
     int32_t *trp = trace_off >= 0 ? trace + 2 * (trace_off + t0) : nullptr;
     int32_t *scp = score_off >= 0 ? scores + score_off + t0 * n : nullptr;
     int32_t ts = 0;
 
-    while (ts < nsteps && !stop) {
-        // Keep per-lane index arithmetic inside the loop instead of pinning ~100 VGPRs of
-        // loop invariants for the whole walk: the values are cheap to recompute and the
-        // registers are worth more as occupancy.
-        asm volatile("" : "+v"(w.lane));
-        w.prepare();
-        int32_t isl_j[G];
-        w.score(isl_j);
-        uint32_t keys[G];
-#pragma unroll
-        for (int g = 0; g < G; g++) {
-            const int j = w.lane + 64 * g;
-            keys[g] = (j < n) ? (((uint32_t)isl_j[g] << 8) | (uint32_t)j) : 0xFFFFFFFFu;
-            if (scp && j < n)
-                scp[j] = isl_j[g];
-        }
-
-        // best non-visited flip: take the PW smallest keys, probe them together
-        int js = -1;
-        int32_t isl_new = 0;
-        while (true) {
-            uint32_t cand[PW];
-#pragma unroll
-            for (int i = 0; i < PW; i++) {
-                uint32_t km = keys[0];
-#pragma unroll
-                for (int g = 1; g < G; g++)
-                    km = min(km, keys[g]);
-                cand[i] = wave_min_u32(km);
-                if (cand[i] != 0xFFFFFFFFu) {
-#pragma unroll
-                    for (int g = 0; g < G; g++)
-                        keys[g] = (w.lane + 64 * g == (int)(cand[i] & 255u)) ? 0xFFFFFFFFu : keys[g];
-                }
+    // The hot loop below only ever commits moves; restarts (a trap, or a periodic one) leave it
+    // and are done by the outer loop, so the loop-carried walk state stays in scalar registers.
+    bool need_restart = false;
+    int32_t *trap_trp = nullptr; // trace record of a trap step, written once the restart is done
+    while (true) {
+        if (need_restart) {
+            need_restart = false;
+            restarts++;
+            restart_idx++;
+            start_bits(seed, walk_id, (uint32_t)restart_idx, n, w.x);
+            clear_table(T, tlog2);
+            w.rebuild();
+            if (lane == 0)
+                T[slot_of(w.h, w.x[0], exact, tlog2)] = w.h | 1ull;
+            if (trap_trp && lane == 0) {
+                trap_trp[0] = -1;
+                trap_trp[1] = w.isl;
             }
-            if (cand[0] == 0xFFFFFFFFu)
-                break; // every flip leads to a visited state
-            // lane i probes candidate i
-            uint32_t my = cand[0];
+            trap_trp = nullptr;
+        }
+        while (ts < nsteps && !stop) {
+            // Keep per-lane index arithmetic inside the loop instead of pinning ~100 VGPRs of
+            // loop invariants for the whole walk: the values are cheap to recompute and the
+            // registers are worth more as occupancy.
+            asm volatile("" : "+v"(w.lane));
+            w.prepare();
+            int32_t isl_j[G];
+            w.score(isl_j);
+            uint32_t keys[G];
 #pragma unroll
-            for (int i = 1; i < PW; i++)
-                my = (w.lane == i) ? cand[i] : my;
-            const int jm = min((int)(my & 255u), n - 1);
-            const uint64_t hc = w.h ^ zk[jm];
-            uint32_t x0 = w.x[0] ^ (1u << (jm & 31));
-            if (jm >= 32)
-                x0 = w.x[0];
-            uint64_t got = 0;
-            if (w.lane < PW && my != 0xFFFFFFFFu)
-                got = T[slot_of(hc, x0, exact, tlog2)];
-            const bool fresh = (w.lane < PW) && (my != 0xFFFFFFFFu) && (got != (hc | 1ull));
-            const uint64_t okmask = ballot(fresh);
-            if (okmask != 0ull) {
-                const int first = __builtin_ctzll(okmask);
-                uint32_t pick = cand[0];
+            for (int g = 0; g < G; g++) {
+                const int j = w.lane + 64 * g;
+                keys[g] = (j < n) ? (((uint32_t)isl_j[g] << 8) | (uint32_t)j) : 0xFFFFFFFFu;
+                if (scp && j < n)
+                    scp[j] = isl_j[g];
+            }
+
+            // best non-visited flip: take the PW smallest keys, probe them together
+            int js = -1;
+            int32_t isl_new = 0;
+            while (true) {
+                uint32_t cand[PW];
+#pragma unroll
+                for (int i = 0; i < PW; i++) {
+                    uint32_t km = keys[0];
+#pragma unroll
+                    for (int g = 1; g < G; g++)
+                        km = min(km, keys[g]);
+                    cand[i] = wave_min_u32(km);
+                    if (cand[i] != 0xFFFFFFFFu) {
+#pragma unroll
+                        for (int g = 0; g < G; g++)
+                            keys[g] = (w.lane + 64 * g == (int)(cand[i] & 255u)) ? 0xFFFFFFFFu : keys[g];
+                    }
+                }
+                if (cand[0] == 0xFFFFFFFFu)
+                    break; // every flip leads to a visited state
+                // lane i probes candidate i
+                uint32_t my = cand[0];
 #pragma unroll
                 for (int i = 1; i < PW; i++)
-                    pick = (first == i) ? cand[i] : pick;
-                js = (int)(pick & 255u);
-                isl_new = (int32_t)(pick >> 8);
+                    my = (w.lane == i) ? cand[i] : my;
+                const int jm = min((int)(my & 255u), n - 1);
+                const uint64_t hc = w.h ^ zk[jm];
+                uint32_t x0 = w.x[0] ^ (1u << (jm & 31));
+                if (jm >= 32)
+                    x0 = w.x[0];
+                uint64_t got = 0;
+                if (w.lane < PW && my != 0xFFFFFFFFu)
+                    got = T[slot_of(hc, x0, exact, tlog2)];
+                const bool fresh = (w.lane < PW) && (my != 0xFFFFFFFFu) && (got != (hc | 1ull));
+                const uint64_t okmask = ballot(fresh);
+                if (okmask != 0ull) {
+                    const int first = __builtin_ctzll(okmask);
+                    uint32_t pick = cand[0];
+#pragma unroll
+                    for (int i = 1; i < PW; i++)
+                        pick = (first == i) ? cand[i] : pick;
+                    js = (int)(pick & 255u);
+                    isl_new = (int32_t)(pick >> 8);
+                    break;
+                }
+                if (cand[PW - 1] == 0xFFFFFFFFu)
+                    break;
+            }
+
+            ts++;
+            rem--;
+            if (js < 0) {
+                // trapped: every flip leads to a visited state; restart (the step counts, and
+                // replaces a periodic restart due at the same step)
+                traps++;
+                if (rem == 0)
+                    rem = R32;
+                trap_trp = trp;
+                if (trp)
+                    trp += 2;
+                if (scp)
+                    scp += n;
+                need_restart = true;
                 break;
             }
-            if (cand[PW - 1] == 0xFFFFFFFFu)
-                break;
-        }
-
-        ts++;
-        rem--;
-        bool restart_now;
-        if (js < 0) {
-            // trapped: every flip leads to a visited state; restart (the step counts)
-            traps++;
-            restart_now = true;
-        } else {
             w.commit(js, isl_new);
             if (w.lane == 0)
                 T[slot_of(w.h, w.x[0], exact, tlog2)] = w.h | 1ull;
-            if (trp && w.lane == 0) {
-                trp[0] = js;
-                trp[1] = w.isl;
+            if (trp) {
+                if (w.lane == 0) {
+                    trp[0] = js;
+                    trp[1] = w.isl;
+                }
+                trp += 2;
             }
+            if (scp)
+                scp += n;
             if (w.isl < best32) {
                 best32 = w.isl;
-                best_step = t0 + ts;
+                best_ts = ts;
 #pragma unroll
                 for (int i = 0; i < kXWords; i++)
                     best_x[i] = w.x[i];
             }
             if (tgt >= 0 && !hit_found && w.isl <= tgt) {
                 hit_found = true;
-                hit = t0 + ts;
+                hit_ts = ts;
                 stop = true;
             }
             if (wch >= 0 && !watch_found && w.isl <= wch) {
                 watch_found = true;
-                wstep = t0 + ts;
+                watch_ts = ts;
             }
-            // periodic restart (not after the last step, not once stopped)
-            restart_now = rem == 0 && t0 + ts < steps && !stop;
-        }
-        if (rem == 0)
-            rem = R32; // a trap restart replaces a periodic one due at the same step
-        if (restart_now) {
-            restarts++;
-            restart_idx++;
-            start_bits(seed, walk_id, (uint32_t)restart_idx, n, w.x);
-            clear_table(T, tlog2);
-            w.rebuild();
-            if (w.lane == 0)
-                T[slot_of(w.h, w.x[0], exact, tlog2)] = w.h | 1ull;
-        }
-        if (trp) {
-            if (js < 0 && w.lane == 0) {
-                trp[0] = -1;
-                trp[1] = w.isl;
+            if (rem == 0) {
+                rem = R32;
+                // periodic restart (not after the last step, not once stopped)
+                if (ts < left32 && !stop) {
+                    need_restart = true;
+                    break;
+                }
             }
-            trp += 2;
         }
-        if (scp)
-            scp += n;
+        if (!need_restart)
+            break;
     }
     t = t0 + ts;
     flips = flips0 + (int64_t)ts * n;
     best_isl = best32;
+    if (best_ts >= 0)
+        best_step = t0 + best_ts;
+    if (hit_ts >= 0)
+        hit = t0 + hit_ts;
+    if (watch_ts >= 0)
+        wstep = t0 + watch_ts;
 
     if (lane == 0) {
         ws.t = t;
@@ -771,7 +805,9 @@ __global__ void __launch_bounds__(64 * kMaxWavesPerBlock) k_walk(WalkState *__re
     __shared__ uint64_t zk[kNMax];
     extern __shared__ __align__(16) unsigned char dyn_smem[];
     fill_zobrist(zk);
-    const int wave = (int)(threadIdx.x >> 6);
+    // wave index within the block: uniform across the wave, said so explicitly so that every
+    // value derived from it (walk index, state pointer, LDS block) stays in scalar registers
+    const int wave = (int)uniform(threadIdx.x >> 6);
     const int wpb = (int)(blockDim.x >> 6);
     Lds *lds = reinterpret_cast<Lds *>(dyn_smem) + wave;
     // one walk per wave (counter == nullptr), or the persistent form: every wave pulls walks
