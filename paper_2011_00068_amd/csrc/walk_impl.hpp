@@ -96,6 +96,23 @@ __device__ inline void start_bits(uint64_t seed, uint32_t walk_id, uint32_t rest
 }
 
 // ---------------------------------------------------------------------------------------------
+// Per-lane constants of the bit-sliced scoring of one flip j (they depend only on L and j, so a
+// walk computes them once and keeps them in registers; the per-step work then reads them).
+// ---------------------------------------------------------------------------------------------
+struct FlipConst {
+    const uint32_t *wp; // par[j&1] word holding bit hj+1 (start of the p window)
+    const uint32_t *wq; // rev[j&1] word holding bit kNA-hj (start of the q window)
+    uint32_t sp;        // p-window shift hj+1; the q-window shift kNA-hj = 1 - sp (mod 32)
+    const int32_t *psx_np, *psx_nq; // PSX at the counts of valid p / q shifts
+    const int32_t *c_kd;            // C at the excluded shift d = L-1-2j
+    const uint32_t *qd_word;        // par word holding b_{j-d} (j - d >= 0 iff 3 j >= 2 c)
+    uint32_t qd_shift;              // its bit
+    uint32_t m_par;                 // (c - j) & 1: s_m = (-1)^(c-j) s_j
+    int32_t hconst;                 // np + 3 nq - 1 (H_j without the data-dependent terms)
+    int32_t nq;                     // valid q shifts: floor(j/2)
+};
+
+// ---------------------------------------------------------------------------------------------
 // The walker: one wave's view of one walk.
 //   G  = flip groups (n <= 64 G), KW = 32-bit words of a shift window (c <= 32 KW).
 // ---------------------------------------------------------------------------------------------
@@ -114,6 +131,33 @@ struct Walker {
     int planes;
     Lds *lds;
     const uint64_t *zk;
+    FlipConst fc[G];
+
+    // Per-lane constants of the owned flips (bit-sliced variant).
+    __device__ __forceinline__ void setup_lanes(int ln)
+    {
+#pragma unroll
+        for (int g = 0; g < G; g++) {
+            const int j = min(ln + 64 * g, c);
+            const int p = j & 1, hj = j >> 1;
+            const int nq = hj;
+            const int np = c - ((j + 1) >> 1);
+            FlipConst &f = fc[g];
+            f.sp = (uint32_t)(hj + 1);
+            f.wp = &lds->par[p][(hj + 1) >> 5];
+            f.wq = &lds->rev[p][(kNA - hj) >> 5];
+            f.psx_np = &lds->psx[np];
+            f.psx_nq = &lds->psx[nq];
+            f.c_kd = &lds->C[max(c - 1 - j, 0)];
+            const int iq = 3 * j - 2 * c;
+            const int a = max(iq, 0) >> 1;
+            f.qd_word = &lds->par[p][a >> 5];
+            f.qd_shift = (uint32_t)(a & 31);
+            f.m_par = (uint32_t)((c - j) & 1);
+            f.hconst = np + 3 * nq - 1;
+            f.nq = nq;
+        }
+    }
 
     // b_i of the full sequence (Eq. (4) mirror for i > c), read from the LDS copy of x.
     __device__ inline uint32_t seq_bit(int i) const
@@ -241,25 +285,19 @@ struct Walker {
             uint32_t wq[G][G];
 #pragma unroll
             for (int g = 0; g < G; g++) {
-                const int j = lane + 64 * g;
-                const int p = j & 1;
-                const int hj = j >> 1;
-                const int sp = hj + 1;
-                const uint32_t *P = lds->par[p];
-                uint32_t lo = P[sp >> 5];
+                const FlipConst &f = fc[g];
+                uint32_t lo = f.wp[0];
 #pragma unroll
                 for (int w = 0; w < KW - g; w++) {
-                    const uint32_t hi = P[(sp >> 5) + w + 1];
-                    wp[g][w] = funnel(hi, lo, sp & 31);
+                    const uint32_t hi = f.wp[w + 1];
+                    wp[g][w] = funnel(hi, lo, (int)f.sp);
                     lo = hi;
                 }
-                const int sq = kNA - hj;
-                const uint32_t *R = lds->rev[p];
-                lo = R[sq >> 5];
+                lo = f.wq[0];
 #pragma unroll
                 for (int w = 0; w <= g; w++) {
-                    const uint32_t hi = R[(sq >> 5) + w + 1];
-                    wq[g][w] = funnel(hi, lo, sq & 31);
+                    const uint32_t hi = f.wq[w + 1];
+                    wq[g][w] = funnel(hi, lo, (int)(1u - f.sp));
                     lo = hi;
                 }
             }
@@ -307,36 +345,33 @@ struct Walker {
                     acc[g] = (int32_t)s;
                 }
             }
-            // assemble ISL_j (branch-free; products with +-1 are conditional negations).  For the
-            // centre, Wp equals Wq (Eq. (4) mirrors every even offset onto itself), so
-            // acc = 2 sum C Wq and G_c = PSX[nq] - acc, H_c = nq.
+            // assemble ISL_j (products with +-1 are conditional negations).  For the centre, Wp
+            // equals Wq (Eq. (4) mirrors every even offset onto itself), so acc = 2 sum C Wq and
+            // G_c = PSX[nq] - acc, H_c = nq.
 #pragma unroll
             for (int g = 0; g < G; g++) {
-                const int j = lane + 64 * g;
-                const int jc = min(j, c);
-                const bool centre = jc == c;
-                const int nq = jc >> 1;
-                const int np = c - ((jc + 1) >> 1);
-                // R_j = sum over shifts valid on both sides of s_{j+k} s_{j-k}; both sides are
-                // valid exactly for kappa < nq, and nq lies in [32 g, 32 g + 31]
+                const FlipConst &f = fc[g];
+                // R_j = nq - 2 rc, rc = differing bits of Wp and Wq over the both-sided shifts
                 uint32_t rc = 0;
 #pragma unroll
                 for (int w = 0; w < g; w++)
                     rc = bcnt_acc((w < KW - g ? wp[g][w] : 0u) ^ wq[g][w], rc);
-                rc = bcnt_acc(((g < KW - g ? wp[g][g] : 0u) ^ wq[g][g]) & ((1u << ((nq - 32 * g) & 31)) - 1u), rc);
-                const int kd = max(c - 1 - jc, 0);
-                const int32_t Cd = lds->C[kd];
-                const bool m_neg = (sbit[g] ^ ((c - jc) & 1)) != 0; // s_m = -1
-                const int iq = 3 * jc - 2 * c; // index j - d of the far partner of the excluded pair
-                const int a = max(iq, 0) >> 1;
-                const uint32_t qbit = (lds->par[jc & 1][a >> 5] >> (a & 31)) & 1u;
-                // s_m q_d in {-1, 0, +1}: 0 when j - d < 0, else the sign of s_m s_{j-d}
-                const int32_t smqd = (iq >= 0) ? (((uint32_t)m_neg ^ qbit) ? -1 : 1) : 0;
-                const int32_t psq = lds->psx[nq];
-                const int32_t Gg = lds->psx[np] + psq - 2 * acc[g] - (m_neg ? -Cd : Cd);
-                const int32_t Hg = np + nq + 2 * nq - 4 * (int32_t)rc - 1 - 2 * smqd; // 2 R_j = 2 nq - 4 rc
-                const int32_t Gj = centre ? psq - acc[g] : Gg;
-                const int32_t Hj = centre ? nq : Hg;
+                // nq lies in [32 g, 32 g + 31]: the low (nq - 32 g) bits of word g are both-sided
+                const uint32_t rmask = (1u << (f.nq & 31)) - 1u;
+                rc = bcnt_acc(((g < KW - g ? wp[g][g] : 0u) ^ wq[g][g]) & rmask, rc);
+                const int32_t Cd = *f.c_kd;
+                const int32_t pnp = *f.psx_np, pnq = *f.psx_nq;
+                const uint32_t qbit = (*f.qd_word >> f.qd_shift) & 1u;
+                const uint32_t m_neg = (uint32_t)sbit[g] ^ f.m_par; // s_m = -1
+                // s_m q_d in {-1, 0, +1}
+                const int j = this->lane + 64 * g;
+                const bool centre = j == c;
+                const bool qd_valid = 3 * j >= 2 * c; // j - d >= 0
+                const int32_t smqd = qd_valid ? ((m_neg ^ qbit) ? -1 : 1) : 0;
+                const int32_t Gg = pnp + pnq - 2 * acc[g] - (m_neg ? -Cd : Cd);
+                const int32_t Hg = f.hconst - 4 * (int32_t)rc - 2 * smqd; // np + nq + 2 R_j - 1 - 2 s_m q_d
+                const int32_t Gj = centre ? pnq - acc[g] : Gg;
+                const int32_t Hj = centre ? f.nq : Hg;
                 // ISL - 8 s_j G_j + 16 H_j
                 isl_j[g] = isl + (sbit[g] ? 8 * Gj : -8 * Gj) + 16 * Hj;
             }
@@ -470,6 +505,8 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
     w.n = w.c + 1;
     w.lds = lds;
     w.zk = zk;
+    if constexpr (!DIRECT)
+        w.setup_lanes(lane);
     const int L = w.L, n = w.n;
     const int tlog2 = su(ws.table_log2);
     const bool exact = n <= tlog2;
@@ -850,6 +887,8 @@ __global__ void __launch_bounds__(64) k_flip_scores(int L, int count, const uint
     w.n = w.c + 1;
     w.lds = &lds;
     w.zk = zk;
+    if constexpr (!DIRECT)
+        w.setup_lanes(w.lane);
 #pragma unroll
     for (int i = 0; i < kXWords; i++)
         w.x[i] = xs[(int64_t)r * kXWords + i];
