@@ -18,6 +18,14 @@
  *   Free-bit vector x: bit j (word j/64, bit j%64) = b_j, j = 0..c.
  *
  * Every accumulator is int64.
+ *
+ * Pins: Eq. (1)-(4), PSL, the hex codec and the one-flip evaluation are pinned by Table 1, the
+ * Barker-13 worked case, numpy.correlate, brute force over all 2^L sequences and the plain
+ * definition of a flipped ISL (tests/test_oracle_*.py); SplitMix64 by its published first outputs.
+ * Parity unpinned: ref_start_bits, ref_zobrist and the visited-table, tie and restart rules of
+ * ref_walk are readings of what the paper leaves open; they are checked only for internal
+ * consistency (incremental walk == recomputing walk, bounded table == exact set before any
+ * eviction, no revisits, best == first minimum of the trajectory).
  */
 #include <stdint.h>
 #include <stdlib.h>
