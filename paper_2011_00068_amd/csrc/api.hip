@@ -659,7 +659,8 @@ static int resolve_opts(labs_walk_plan *p, const labs_plan_opts *in)
         if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
             cus = prop.multiProcessorCount;
     }
-    p->lp.grid_waves = std::min<int32_t>(p->n_walks, cus * 16);
+    const int resident = resident_walk_waves(p->lp);
+    p->lp.grid_waves = std::min<int32_t>(p->n_walks, resident > 0 ? resident : cus * 8);
     const int64_t per = o.steps_per_launch;
     p->launches_per_run = (int32_t)std::max<int64_t>(1, (p->max_steps + per - 1) / per);
     return LABS_OK;

@@ -63,6 +63,8 @@ struct WalkLaunch {
 // Kernel instantiation for length L: flip groups G = ceil(n/64), table words KW = ceil(c/32).
 int shape_for_length(int L);
 int shape_groups(int shape);
+// Waves of the walk kernel chosen by lp that fit on the device at once (0 if unknown).
+int resident_walk_waves(const WalkLaunch &lp);
 
 // Launch wrappers (walk_kernels.hip).
 hipError_t launch_walk(const WalkLaunch &lp, WalkState *states, int32_t n_walks,

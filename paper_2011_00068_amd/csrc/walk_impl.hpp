@@ -831,8 +831,13 @@ __device__ __forceinline__ void run_any(WalkState *ws, uint64_t *tables, int32_t
 constexpr int kMaxWavesPerBlock = 8;
 
 
+// Occupancy target of the walk kernel per shape: the smaller shapes fit 8 waves per SIMD (64
+// VGPRs), the 3-group shapes keep more windows in registers.
+template <int SHAPE> struct WavesPerEu { static constexpr int value = (SHAPE >= 0 && SHAPE <= 4) ? 8 : 4; };
+
 template <int SHAPE, bool DIRECT, int PW>
-__global__ void __launch_bounds__(64 * kMaxWavesPerBlock) k_walk(WalkState *__restrict__ states, int32_t n_walks,
+__global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
+    __attribute__((amdgpu_waves_per_eu(WavesPerEu<SHAPE>::value))) k_walk(WalkState *__restrict__ states, int32_t n_walks,
                                               const int32_t *__restrict__ order,
                                               uint64_t *__restrict__ tables, int32_t *__restrict__ trace,
                                               int32_t *__restrict__ scores, int64_t chunk,

@@ -29,15 +29,35 @@ __global__ void k_reset(WalkState *__restrict__ states, const WalkState *__restr
 // Launch wrappers.
 // ---------------------------------------------------------------------------------------------
 
+static WalkKernel pick_kernel(const WalkLaunch &lp)
+{
+    const bool direct = lp.variant == LABS_VARIANT_DIRECT;
+    return direct ? (lp.probe_width >= 2 ? pick_walk_kernel_direct_pw2(lp.shape)
+                                         : pick_walk_kernel_direct_pw1(lp.shape))
+                  : (lp.probe_width >= 2 ? pick_walk_kernel_bits_pw2(lp.shape)
+                                         : pick_walk_kernel_bits_pw1(lp.shape));
+}
+
+int resident_walk_waves(const WalkLaunch &lp)
+{
+    const bool direct = lp.variant == LABS_VARIANT_DIRECT;
+    const int wpb = lp.waves_per_block;
+    const size_t lds = (size_t)wpb * (direct ? sizeof(WaveLdsDirect) : sizeof(WaveLdsBits));
+    int blocks = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void *>(pick_kernel(lp)),
+                                                     64 * wpb, lds) != hipSuccess)
+        return 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return blocks * wpb * cus;
+}
+
 hipError_t launch_walk(const WalkLaunch &lp, WalkState *states, int32_t n_walks, const int32_t *order,
                        uint64_t *tables, int32_t *trace, int32_t *scores, int32_t *counter,
                        hipStream_t stream)
 {
     const bool direct = lp.variant == LABS_VARIANT_DIRECT;
-    WalkKernel k = direct ? (lp.probe_width >= 2 ? pick_walk_kernel_direct_pw2(lp.shape)
-                                                 : pick_walk_kernel_direct_pw1(lp.shape))
-                          : (lp.probe_width >= 2 ? pick_walk_kernel_bits_pw2(lp.shape)
-                                                 : pick_walk_kernel_bits_pw1(lp.shape));
+    WalkKernel k = pick_kernel(lp);
     const int wpb = lp.waves_per_block;
     if (wpb < 1 || wpb > kMaxWavesPerBlock)
         return hipErrorInvalidConfiguration; // the kernel is compiled for at most 8 waves per block
