@@ -207,7 +207,8 @@ int labs_autotune(int32_t L, int32_t n_walks, labs_plan_opts *best);
  * every admitted walk resident across kernel launches and advances all running jobs together
  * (continuous batching).  A job = n_walks walks of one length; each walk's step budget is
  * floor(flip_budget / (n_walks * n)); the job stops at its budget or at the first tick
- * boundary (every steps_per_tick logical steps) after some walk reached ISL <= ISL_T, where
+ * boundary (steps_per_tick, 2 steps_per_tick, ... logical steps) at or after the first step at
+ * which some walk reached ISL <= ISL_T, where
  * ISL_T = floor(L^2 * den / (2 * num)) is the exact integer form of F >= num/den (Eq. (3)).
  * Results are a function of the request alone: they do not depend on what else runs.
  * ------------------------------------------------------------------------------------------- */

@@ -1,0 +1,145 @@
+"""The continuous-batching search server (labs_server_* / labs_search_*) on the GPU: a job's
+result equals the oracle's walks cut at the job's stopping tick, is identical alone and in a mix
+of concurrent jobs, admission respects the device-memory budget, and cancel frees the slots."""
+import random
+import time
+
+import numpy as np
+import pytest
+
+from oracle import oracle as o
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SEED = 2011000068
+TABLE_LOG2 = 12
+PER_WALK_BYTES = (1 << TABLE_LOG2) * 8 + 256 + 4
+
+
+@pytest.fixture(scope="module")
+def labs():
+    import paper_2011_00068_amd as labs
+
+    labs.lib()
+    return labs
+
+
+def oracle_job(L, n_walks, seed, steps, isl_t, tick):
+    """The job semantics written out with the oracle: every walk runs to the step where the job
+    stops (its budget, or the first tick boundary at or after the earliest hit)."""
+    n = (L + 1) // 2
+    full = [o.walk(L, seed, w, steps=steps, table_log2=TABLE_LOG2, watch_isl=isl_t) for w in range(n_walks)]
+    hits = [(r["watch_step"], w) for w, r in enumerate(full) if r["watch_step"] >= 0]
+    end = steps
+    hit_step, hit_walk = -1, -1
+    if isl_t >= 0 and hits:
+        hit_step, hit_walk = min(hits)
+        end = min(steps, max(1, -(-hit_step // tick)) * tick)  # first boundary after the start
+    cut = full if end == steps else [o.walk(L, seed, w, steps=end, table_log2=TABLE_LOG2, watch_isl=isl_t)
+                                      for w in range(n_walks)]
+    best = min((r["best_isl"], w) for w, r in enumerate(cut))
+    return {"best_isl": best[0], "best_walk": best[1], "hit_step": hit_step, "hit_walk": hit_walk,
+            "steps_done": end, "flip_evals": end * n * n_walks,
+            "best_bits": cut[best[1]]["best_bits"]}
+
+
+def job_view(labs, st, L):
+    n = (L + 1) // 2
+    return {"best_isl": st["best_isl"], "best_walk": st["best_walk"], "hit_step": st["hit_step"],
+            "hit_walk": st["hit_walk"], "steps_done": st["steps_done"], "flip_evals": st["flip_evals"],
+            "best_bits": labs.words_to_int(st["best_bits_words"], n)}
+
+
+def test_single_job_matches_oracle_without_target(labs):
+    srv = labs.Server(device_mem_bytes=64 * PER_WALK_BYTES, table_log2=TABLE_LOG2, steps_per_tick=64)
+    L, W, budget = 61, 6, 6 * 31 * 500
+    jid = srv.submit(L, W, SEED, budget)
+    done, st = srv.wait(jid, timeout_ms=60000)
+    srv.close()
+    assert done and st["state"] == labs.JOB_DONE
+    want = oracle_job(L, W, SEED, budget // (W * 31), -1, 64)
+    assert job_view(labs, st, L) == want
+    assert st["best_F"] == pytest.approx(L * L / (2 * want["best_isl"]))
+
+
+def test_single_job_stops_at_tick_after_hit(labs):
+    # L = 31: F >= 5 (ISL <= 96) is reached within a few hundred steps; the job stops at the first
+    # 32-step boundary after the earliest hit and reports every walk's best up to there.
+    srv = labs.Server(device_mem_bytes=64 * PER_WALK_BYTES, table_log2=TABLE_LOG2, steps_per_tick=32)
+    L, W = 31, 4
+    budget = W * 16 * 5000
+    jid = srv.submit(L, W, SEED + 1, budget, target_F=(5, 1))
+    done, st = srv.wait(jid, timeout_ms=60000)
+    srv.close()
+    assert done
+    isl_t = labs.isl_threshold(L, 5, 1)
+    assert isl_t == (31 * 31) // 10
+    want = oracle_job(L, W, SEED + 1, budget // (W * 16), isl_t, 32)
+    assert want["hit_step"] >= 0
+    assert job_view(labs, st, L) == want
+
+
+def test_alone_equals_mix(labs):
+    # the same request alone, and submitted while other jobs of other lengths come and go
+    req = (101, 5, 777, 5 * 51 * 700, (9, 2))
+    srv = labs.Server(device_mem_bytes=40 * PER_WALK_BYTES, table_log2=TABLE_LOG2, steps_per_tick=50)
+    jid = srv.submit(*req[:4], target_F=req[4])
+    _, alone = srv.wait(jid, timeout_ms=60000)
+    srv.close()
+
+    srv = labs.Server(device_mem_bytes=40 * PER_WALK_BYTES, table_log2=TABLE_LOG2, steps_per_tick=50)
+    rng = random.Random(5)
+    others = []
+    for i in range(4):
+        L = rng.choice([33, 63, 201, 255])
+        others.append(srv.submit(L, rng.randint(3, 12), 100 + i, rng.randint(1, 4) * 20000, target_F=(6, 1)))
+    time.sleep(0.01)
+    jid = srv.submit(*req[:4], target_F=req[4])
+    for i in range(4):
+        L = rng.choice([101, 301])
+        others.append(srv.submit(L, rng.randint(2, 9), 200 + i, 60000))
+    _, mixed = srv.wait(jid, timeout_ms=120000)
+    for j in others:
+        done, _ = srv.wait(j, timeout_ms=120000)
+        assert done
+    stats = srv.stats()
+    srv.close()
+    assert stats["peak_walks"] <= 40
+    assert job_view(labs, alone, 101) == job_view(labs, mixed, 101)
+    assert alone["state"] == mixed["state"] == labs.JOB_DONE
+
+
+def test_admission_by_memory_and_cancel(labs):
+    srv = labs.Server(device_mem_bytes=16 * PER_WALK_BYTES, table_log2=TABLE_LOG2, steps_per_tick=64)
+    with pytest.raises(labs.LabsError) as e:
+        srv.submit(63, 17, SEED, 10 ** 6)  # can never fit the budget
+    assert e.value.code == labs.LABS_ENOMEM
+    long_job = srv.submit(255, 10, SEED, 10 * 128 * 10 ** 6)  # far more steps than the test waits
+    queued = [srv.submit(63, 8, SEED + i, 8 * 32 * 300) for i in range(3)]
+    time.sleep(0.2)
+    done, st = srv.poll(queued[0])
+    assert st["state"] in (labs.JOB_QUEUED, labs.JOB_RUNNING)
+    srv.cancel(long_job)
+    for j in queued:
+        done, st = srv.wait(j, timeout_ms=60000)
+        assert done and st["state"] == labs.JOB_DONE
+    done, st = srv.wait(long_job, timeout_ms=60000)
+    assert done and st["state"] == labs.JOB_CANCELLED
+    stats = srv.stats()
+    assert stats["peak_walks"] <= 16
+    with pytest.raises(labs.LabsError) as e:
+        srv.poll(10 ** 9)
+    assert e.value.code == labs.LABS_ENOTFOUND
+    srv.close()
+
+
+def test_zero_budget_job(labs):
+    srv = labs.Server(device_mem_bytes=8 * PER_WALK_BYTES, table_log2=TABLE_LOG2, steps_per_tick=16)
+    jid = srv.submit(31, 2, SEED, 0)
+    done, st = srv.wait(jid, timeout_ms=30000)
+    srv.close()
+    assert done and st["steps_done"] == 0 and st["flip_evals"] == 0
+    starts = [o.isl(o.skew_expand(31, o.start_bits(31, SEED, w, 0))) for w in range(2)]
+    assert st["best_isl"] == min(starts)

@@ -156,23 +156,26 @@ def test_launch_options_do_not_change_results(labs):
         assert_same(ref[i], oracle_walk(cfgs[i], trace=True), i)
 
 
-def test_l255_headline_sample(labs):
-    # the L = 255 headline workload's launch shape (here 2,048 walks x 4,768 steps, restart
-    # period 2^20, stop at F >= 8.5): sampled walks against the oracle, invariants on all
-    target = (255 * 255 * 2) // (2 * 17)  # F >= 8.5 <=> ISL <= floor(L^2 / (2 * 8.5))
-    cfgs = [labs.make_cfg(255, SEED, w, steps=4768, restart_period=1 << 20, target_isl=target)
-            for w in range(2048)]
+def test_l255_headline_full_size(labs):
+    # the L = 255 headline workload exactly as bench.py runs it (16,384 walks x 4,768 steps, restart
+    # period 2^20, stop at F >= 8.5, watch F >= 8): sampled walks against the oracle, properties on
+    # a stride of the rest
+    import bench
+
+    cfgs = bench.cfgs(labs, bench.WALKS, bench.STEPS)
     plan = labs.WalkPlan(cfgs)
     plan.run()
     res = plan.results()
     plan.close()
-    for w in (0, 1, 777, 2047):
+    for w in (0, 1, 8191, 16383):
         assert_same(res[w], oracle_walk(cfgs[w]), w)
-    for w in range(0, 2048, 97):
+    for w in range(0, bench.WALKS, 61):
         r = res[w]
+        assert r["steps_done"] == bench.STEPS or r["hit_step"] >= 0
         assert r["flip_evals"] == r["steps_done"] * 128
         assert o.isl(o.skew_expand(255, r["best_bits"])) == r["best_isl"]
         assert o.isl(o.skew_expand(255, r["final_bits"])) == r["final_isl"]
+        assert r["best_isl"] <= r["final_isl"]
 
 
 def test_walk_batch_entry_point(labs):

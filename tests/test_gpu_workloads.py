@@ -1,0 +1,72 @@
+"""The other full-size workloads on the GPU, through the C ABI: the L = 101 batch (1,024 walks x
+10^5 steps) with sampled walks against the oracle, and the uneven batch of every odd L in
+[201, 303] x 64 walks x 10^6 steps in one launch, checked by properties that hold at any size
+(each walk's best / final ISL is the ISL of its best / final bits, evaluation counts) and by
+invariance under splitting the walks over several launches."""
+import numpy as np
+import pytest
+
+from oracle import oracle as o
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SEED = 2011000068
+
+
+@pytest.fixture(scope="module")
+def labs():
+    import paper_2011_00068_amd as labs
+
+    labs.lib()
+    return labs
+
+
+def test_l101_batch_full_size(labs):
+    cfgs = [labs.make_cfg(101, SEED, w, steps=100000, table_log2=16) for w in range(1024)]
+    plan = labs.WalkPlan(cfgs)
+    plan.run()
+    res = plan.results()
+    plan.close()
+    for w in (0, 513):
+        r = o.walk(101, SEED, w, steps=100000, table_log2=16)
+        for k in ("best_isl", "best_step", "final_isl", "best_bits", "final_bits", "restarts", "traps", "flip_evals"):
+            assert res[w][k] == r[k], (w, k)
+    for w in range(0, 1024, 37):
+        r = res[w]
+        assert r["steps_done"] == 100000 and r["flip_evals"] == 100000 * 51
+        assert o.isl(o.skew_expand(101, r["best_bits"])) == r["best_isl"]
+        assert o.isl(o.skew_expand(101, r["final_bits"])) == r["final_isl"]
+
+
+def test_uneven_batch_full_size(labs):
+    lengths = list(range(201, 304, 2))
+    cfgs = [labs.make_cfg(L, SEED, w, steps=10 ** 6, table_log2=16) for L in lengths for w in range(64)]
+    one = labs.WalkPlan(cfgs)  # one launch, all 3,328 walks, mixed shapes
+    one.run()
+    res = one.results()
+    ms, launches = one.last_timing()
+    one.close()
+    assert launches == 1
+    split = labs.WalkPlan(cfgs, steps_per_launch=333333, persistent=2)  # 4 launches, pulled walks
+    split.run()
+    res2 = split.results()
+    split.close()
+    for a, b in zip(res, res2):
+        assert a == b
+    for i in range(0, len(cfgs), 53):
+        L = cfgs[i].L
+        r = res[i]
+        assert r["steps_done"] == 10 ** 6 and r["flip_evals"] == 10 ** 6 * ((L + 1) // 2)
+        assert o.isl(o.skew_expand(L, r["best_bits"])) == r["best_isl"]
+        assert o.isl(o.skew_expand(L, r["final_bits"])) == r["final_isl"]
+    # the uneven batch shares its first steps with a short run of the same walks
+    short = [labs.make_cfg(L, SEED, 0, steps=300, table_log2=16, trace=True) for L in lengths[::9]]
+    p = labs.WalkPlan(short)
+    p.run()
+    rs = p.results()
+    p.close()
+    for c, r in zip(short, rs):
+        ref = o.walk(c.L, SEED, 0, steps=300, table_log2=16, trace=True)
+        assert np.array_equal(r["trace"], ref["trace"])
