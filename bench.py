@@ -123,6 +123,65 @@ def plain_form(labs, walks=32):
             "time_to_F8": time_to_f8(res, per_walk_ms, STEPS)}, res
 
 
+def serving(labs, rate=20.0, n_requests=100, seed=SEED):
+    """The serving workload: Poisson arrivals (seeded), each request one odd L uniform in
+    [201, 303] with 256 walks, 10^8 flip evaluations and stop threshold F >= 8, admitted by device
+    memory for walk state.  Returns latency percentiles and aggregate throughput."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=n_requests)
+    lengths = rng.choice(np.arange(201, 304, 2), size=n_requests)
+    srv = labs.Server(device_mem_bytes=8 << 30, table_log2=TABLE_LOG2, steps_per_tick=256)
+    t0 = time.perf_counter()
+    jobs = []
+    next_t = 0.0
+    for i in range(n_requests):
+        next_t += gaps[i]
+        delay = next_t - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        jobs.append((int(lengths[i]), srv.submit(int(lengths[i]), 256, seed + i, 10 ** 8, target_F=(8, 1))))
+    lat, flips, hits = [], 0, 0
+    for L, j in jobs:
+        done, st = srv.wait(j, timeout_ms=600000)
+        lat.append(st["t_done"] - st["t_submit"])
+        flips += st["flip_evals"]
+        hits += st["hit_step"] >= 0
+    wall = time.perf_counter() - t0
+    stats = srv.stats()
+    srv.close()
+    lat = np.sort(np.array(lat))
+    return {"requests": n_requests, "rate_per_s": rate, "walks_per_request": 256,
+            "flip_budget_per_request": 10 ** 8, "target_F": 8.0,
+            "p50_latency_s": float(lat[int(0.50 * (len(lat) - 1))]),
+            "p99_latency_s": float(lat[int(0.99 * (len(lat) - 1))]),
+            "aggregate_flip_evals_per_s": flips / wall, "hit_fraction": hits / n_requests,
+            "wall_s": wall, "ticks": stats["ticks"], "peak_resident_walks": stats["peak_walks"]}
+
+
+def uneven_batch(labs):
+    """Every odd L in [201, 303] x 64 walks x 10^6 steps in one launch (mixed shapes)."""
+    import torch
+
+    cfg = [labs.make_cfg(L, SEED, w, steps=10 ** 6, table_log2=TABLE_LOG2) for L in range(201, 304, 2)
+           for w in range(64)]
+    plan = labs.WalkPlan(cfg)
+    plan.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.run()
+    ms, launches = plan.last_timing()
+    wall = time.perf_counter() - t0
+    res = plan.results()
+    plan.close()
+    flips = sum(r["flip_evals"] for r in res)
+    return {"walks": len(cfg), "steps_per_walk": 10 ** 6, "launches": launches, "kernel_ms": ms,
+            "flip_evals_per_s": flips / wall,
+            "alg_ops_frac_of_valu_peak": sum(r["flip_evals"] * 3 * (c.L - 1) // 2 for r, c in zip(res, cfg))
+            / (ms / 1000.0) / (VALU_PEAK_TOPS * 1e12)}
+
+
 def traffic_per_launch():
     """HBM bytes per walk launch from the committed rocprofv3 counter summary, if it was taken
     on the current kernel source; else None."""
@@ -143,6 +202,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the serving and uneven-batch measurements")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -219,6 +280,9 @@ def main():
     }
     if not args.no_plain:
         line["plain_form"], _ = plain_form(labs)
+    if not args.no_extras:
+        line["uneven_batch"] = uneven_batch(labs)
+        line["serving"] = serving(labs)
     if not args.no_cpu:
         line["cpu_baseline"], _ = cpu_baseline()
     print(json.dumps(line), flush=True)
