@@ -182,9 +182,10 @@ def uneven_batch(labs):
             / (ms / 1000.0) / (VALU_PEAK_TOPS * 1e12)}
 
 
-def traffic_per_launch():
-    """HBM bytes per walk launch from the committed rocprofv3 counter summary, if it was taken
-    on the current kernel source; else None."""
+def counter_summary():
+    """The committed rocprofv3 counter summary of the walk kernel (HBM bytes per launch scaled by
+    the copy calibration, VALU issue occupancy), if it was taken on the current kernel source;
+    else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -192,7 +193,7 @@ def traffic_per_launch():
         return None
     if t.get("kernel_source_sha256_16") != source_hash():
         return None
-    return t.get("hbm_bytes_per_launch")
+    return t
 
 
 def main():
@@ -254,10 +255,16 @@ def main():
     per_launch_ms = avg_kernel_ms / max(1, launches)
     alg_ops_per_launch = flips_per_job * ALG_OPS_PER_FLIP / max(1, launches)
     achieved = alg_ops_per_launch / (per_launch_ms / 1000.0) / 1e12
+    cnt = counter_summary()
     roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic_per_launch(),
+                "frac": achieved / VALU_PEAK_TOPS,
+                "traffic": cnt["hbm_bytes_per_launch"] if cnt else None,
                 "kernel": "k_walk", "kernel_ms_per_launch": per_launch_ms,
-                "alg_ops_per_flip": ALG_OPS_PER_FLIP}
+                "alg_ops_per_flip": ALG_OPS_PER_FLIP,
+                # rocprofv3 counters of the same launch: share of VALU issue cycles in use, and
+                # VALU instructions per walk step (128 flip evaluations)
+                "counter_valu_issue_frac": cnt["valu_issue_busy_frac"] if cnt else None,
+                "counter_valu_insts_per_step": cnt["valu_insts_per_step"] if cnt else None}
 
     line = {
         "metric": "flip-evals/s at L=255 (batched walks, % INT32 VALU peak); p50 time-to-F>=8",
