@@ -21,7 +21,9 @@
  *
  * Pins: Eq. (1)-(4), PSL, the hex codec and the one-flip evaluation are pinned by Table 1, the
  * Barker-13 worked case, numpy.correlate, brute force over all 2^L sequences and the plain
- * definition of a flipped ISL (tests/test_oracle_*.py); SplitMix64 by its published first outputs.
+ * definition of a flipped ISL (tests/test_oracle_*.py); the grouped skew-space minimum by brute
+ * force over all 2^L sequences and numpy on blocks up to n = 63; SplitMix64 by its published
+ * first outputs.
  * Parity unpinned: ref_start_bits, ref_zobrist and the visited-table, tie and restart rules of
  * ref_walk are readings of what the paper leaves open; they are checked only for internal
  * consistency (incremental walk == recomputing walk, bounded table == exact set before any
@@ -618,5 +620,55 @@ int ref_enum_skew(int32_t L, int64_t *out)
         out[x] = ref_isl(L, s);
     }
     free(s);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------
+ * Minimum over a block of the skew space, grouped by the symmetries of Section 1's search-space
+ * reduction.  Negation (x -> x ^ A, A = all n free bits) and alternation s_i -> (-1)^i s_i
+ * (x -> x ^ O, O = the free bits at odd positions) keep a sequence skew-symmetric and leave its
+ * ISL unchanged; the four sequences {x, x^A, x^O, x^A^O} of a free-bit vector x = r << 2 (bits 0
+ * and 1 clear) are distinct, and every x lies in exactly one such group.  This function covers
+ * the groups of r = r_begin .. r_end - 1 by evaluating all four members of each group from the
+ * definition (Eq. (2), (4)); it does not use the invariance.  Results: the lowest ISL, how many
+ * of the covered sequences reach it, and the lowest such x.  n <= 63.  Returns 0, or -1 on bad
+ * arguments; an empty block gives min_isl = -1, count = 0, first_x = 0.
+ * ---------------------------------------------------------------------------------------- */
+int ref_enum_skew_min(int32_t L, uint64_t r_begin, uint64_t r_end, int64_t *min_isl,
+                      uint64_t *count, uint64_t *first_x)
+{
+    if (L < 3 || (L % 2) == 0)
+        return -1;
+    int32_t n = (L + 1) / 2;
+    if (n > 63 || r_begin > r_end || r_end > ((uint64_t)1 << (n - 2)))
+        return -1;
+    uint64_t all = ((uint64_t)1 << n) - 1, odd = 0;
+    for (int32_t j = 1; j < n; j += 2)
+        odd |= (uint64_t)1 << j;
+    int8_t *s = (int8_t *)malloc((size_t)L);
+    int64_t best = -1;
+    uint64_t cnt = 0, first = 0;
+    for (uint64_t r = r_begin; r < r_end; r++) {
+        uint64_t base = r << 2;
+        uint64_t member[4] = {base, base ^ all, base ^ odd, base ^ all ^ odd};
+        for (int m = 0; m < 4; m++) {
+            uint64_t xw[1] = {member[m]};
+            ref_skew_expand(L, xw, s);
+            int64_t v = ref_isl(L, s);
+            if (best < 0 || v < best) {
+                best = v;
+                cnt = 1;
+                first = member[m];
+            } else if (v == best) {
+                cnt++;
+                if (member[m] < first)
+                    first = member[m];
+            }
+        }
+    }
+    free(s);
+    *min_isl = best;
+    *count = cnt;
+    *first_x = best < 0 ? 0 : first;
     return 0;
 }

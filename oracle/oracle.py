@@ -67,6 +67,8 @@ def lib():
     L.ref_walk.restype = ctypes.c_int
     L.ref_enum_skew.argtypes = [ctypes.c_int32, i64p]
     L.ref_enum_skew.restype = ctypes.c_int
+    L.ref_enum_skew_min.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64, i64p, u64p, u64p]
+    L.ref_enum_skew_min.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -255,3 +257,18 @@ def enum_skew(L: int):
     if rc != 0:
         raise ValueError("enum_skew failed")
     return out
+
+
+def enum_skew_min(L: int, r_begin: int = 0, r_end=None):
+    """Lowest ISL over the symmetry groups r_begin .. r_end - 1 of the skew space (all of it by
+    default): {"min_isl", "count", "first_x", "states"}."""
+    n = (L + 1) // 2
+    if r_end is None:
+        r_end = 1 << (n - 2)
+    mn = ctypes.c_int64()
+    cnt = ctypes.c_uint64()
+    first = ctypes.c_uint64()
+    rc = lib().ref_enum_skew_min(L, r_begin, r_end, ctypes.byref(mn), ctypes.byref(cnt), ctypes.byref(first))
+    if rc != 0:
+        raise ValueError("enum_skew_min: bad arguments")
+    return {"min_isl": mn.value, "count": cnt.value, "first_x": first.value, "states": 4 * (r_end - r_begin)}
