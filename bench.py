@@ -182,6 +182,34 @@ def uneven_batch(labs):
             / (ms / 1000.0) / (VALU_PEAK_TOPS * 1e12)}
 
 
+def enum_alg_ops_per_group(Lx):
+    """Word operations to score one sequence with the bit-packed form of Eq. (1)-(2): for each even
+    lag k, per 32-bit word of the L - k overlapping positions a funnel shift, a masked xor and a
+    popcount-accumulate, then one shift-or and one multiply-add for C_k^2."""
+    return sum(3 * ((Lx - k + 31) // 32) + 2 for k in range(2, Lx, 2))
+
+
+def enumeration(labs, lengths=(61, 69)):
+    """The whole skew space of each length, minimum ISL by exhaustive search on the GPU (one
+    sequence scored per symmetry group of four)."""
+    out = []
+    for Lx in lengths:
+        labs.enum_skew_min(Lx, 0, 1 << 12)  # warm the launch path
+        t0 = time.perf_counter()
+        r = labs.enum_skew_min(Lx)
+        wall = time.perf_counter() - t0
+        groups = r["states"] // 4
+        alg = groups * enum_alg_ops_per_group(Lx) / (r["kernel_ms"] / 1000.0) / 1e12
+        out.append({"L": Lx, "sequences": r["states"], "min_isl": r["min_isl"],
+                    "F": Lx * Lx / (2.0 * r["min_isl"]), "optimal_sequences": r["count"],
+                    "first_x": hex(r["first_x"]), "kernel_ms": r["kernel_ms"], "wall_s": wall,
+                    "sequences_per_s": r["states"] / wall,
+                    "roofline": {"bound": "alu", "achieved": alg, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                                 "frac": alg / VALU_PEAK_TOPS,
+                                 "alg_ops_per_group": enum_alg_ops_per_group(Lx)}})
+    return out
+
+
 def counter_summary():
     """The committed rocprofv3 counter summary of the walk kernel (HBM bytes per launch scaled by
     the copy calibration, VALU issue occupancy), if it was taken on the current kernel source;
@@ -204,7 +232,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the serving and uneven-batch measurements")
+                    help="skip the serving, uneven-batch and enumeration measurements")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -290,6 +318,7 @@ def main():
     if not args.no_extras:
         line["uneven_batch"] = uneven_batch(labs)
         line["serving"] = serving(labs)
+        line["enumeration"] = enumeration(labs)
     if not args.no_cpu:
         line["cpu_baseline"], _ = cpu_baseline()
     print(json.dumps(line), flush=True)

@@ -84,6 +84,31 @@ int labs_isl_batch_dev(int32_t L, int32_t count, const int8_t *s_dev, int64_t *i
  * sequence whose free bits are x.  Odd 3 <= L <= 47 (n <= 24).  Asynchronous on stream. */
 int labs_enum_skew_dev(int32_t L, int32_t *isl_dev, void *stream);
 
+/* Lowest ISL over the skew-symmetric sequences of odd length L, or over a block of them (Eq. (2),
+ * (4); Section 1's search-space reduction), without storing per-sequence values.  Negation
+ * (x -> x ^ A, A = all n free bits) and alternation s_i -> (-1)^i s_i (x -> x ^ O, O = the free
+ * bits at odd positions j) preserve skew symmetry and ISL; group r (0 <= r < 2^(n-2)) is
+ * {x, x^A, x^O, x^A^O} with x = r << 2, and the groups partition the 2^n sequences.  The call
+ * covers groups r_begin .. r_end - 1 (r_begin = 0, r_end = 2^(n-2): the whole space) and reports
+ * the lowest ISL, how many covered sequences reach it (always a multiple of 4), the lowest such
+ * free-bit vector x (bit j = 1 <=> s_j = -1), the sequences covered, and the device time of the
+ * enumeration kernels.  Odd 3 <= L <= 125 (n <= 63).  An empty block (r_begin == r_end) gives
+ * min_isl = -1, count = first_x = states = 0.  Blocking: the work runs on `stream` (NULL = the
+ * default stream) and the call returns when it is done; it allocates and frees a small device
+ * buffer (32 bytes per resident block).  LABS_EINVAL for a bad L, r_begin > r_end or r_end >
+ * 2^(n-2). */
+typedef struct labs_enum_min_result {
+    int32_t min_isl;
+    int32_t reserved;
+    uint64_t count;
+    uint64_t first_x;
+    uint64_t states;
+    double kernel_ms;
+} labs_enum_min_result;
+
+int labs_enum_skew_min(int32_t L, uint64_t r_begin, uint64_t r_end, labs_enum_min_result *out,
+                       void *stream);
+
 /* ---------------------------------------------------------------------------------------------
  * One-flip evaluation (Section 3; Algorithm 1's fast merit-factor step).
  * ------------------------------------------------------------------------------------------- */

@@ -41,7 +41,8 @@ JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_CANCELLED = 0, 1, 2, 3
 # Every symbol include/labs.h declares (checked by the tests).
 EXPORTS = [
     "labs_strerror", "labs_last_error", "labs_device_info",
-    "labs_isl", "labs_merit", "labs_isl_batch_dev", "labs_enum_skew_dev", "labs_flip_scores_dev",
+    "labs_isl", "labs_merit", "labs_isl_batch_dev", "labs_enum_skew_dev", "labs_enum_skew_min",
+    "labs_flip_scores_dev",
     "labs_walk_batch", "labs_walk_plan_create", "labs_walk_plan_run", "labs_walk_plan_results",
     "labs_walk_plan_get_opts", "labs_walk_plan_last_timing", "labs_walk_plan_destroy",
     "labs_autotune",
@@ -101,6 +102,17 @@ class PlanOpts(ctypes.Structure):
         ("steps_per_launch", ctypes.c_int64),
         ("use_graph", ctypes.c_int32),
         ("persistent", ctypes.c_int32),
+    ]
+
+
+class EnumMinResult(ctypes.Structure):
+    _fields_ = [
+        ("min_isl", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("count", ctypes.c_uint64),
+        ("first_x", ctypes.c_uint64),
+        ("states", ctypes.c_uint64),
+        ("kernel_ms", ctypes.c_double),
     ]
 
 
@@ -169,6 +181,7 @@ def lib():
     L.labs_merit.argtypes = [i32, vp, P(ctypes.c_double)]
     L.labs_isl_batch_dev.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp]
     L.labs_enum_skew_dev.argtypes = [i32, vp, vp]
+    L.labs_enum_skew_min.argtypes = [i32, u64, u64, P(EnumMinResult), vp]
     L.labs_flip_scores_dev.argtypes = [i32, i32, vp, vp, i32, vp]
     L.labs_walk_batch.argtypes = [i32, P(WalkCfg), P(WalkResult), vp, vp, vp]
     L.labs_walk_plan_create.argtypes = [i32, P(WalkCfg), P(PlanOpts), P(vp)]
@@ -255,6 +268,18 @@ def enum_skew(L, device="cuda"):
     out = torch.empty(1 << n, dtype=torch.int32, device=device)
     _check(lib().labs_enum_skew_dev(L, _ptr(out), _stream()), "labs_enum_skew_dev")
     return out
+
+
+def enum_skew_min(L, r_begin=0, r_end=None):
+    """Lowest ISL over the symmetry groups r_begin .. r_end - 1 of the odd-length-L skew space
+    (the whole space by default): {"min_isl", "count", "first_x", "states", "kernel_ms"}."""
+    n = (L + 1) // 2
+    if r_end is None:
+        r_end = 1 << max(0, n - 2)
+    res = EnumMinResult()
+    _check(lib().labs_enum_skew_min(L, r_begin, r_end, ctypes.byref(res), _stream()), "labs_enum_skew_min")
+    return {"min_isl": res.min_isl, "count": res.count, "first_x": res.first_x, "states": res.states,
+            "kernel_ms": res.kernel_ms}
 
 
 def x_words(x: int):

@@ -206,6 +206,64 @@ extern "C" int labs_enum_skew_dev(int32_t L, int32_t *isl_dev, void *stream)
     return LABS_OK;
 }
 
+extern "C" int labs_enum_skew_min(int32_t L, uint64_t r_begin, uint64_t r_end, labs_enum_min_result *out,
+                                  void *stream)
+{
+    if (!out)
+        return fail(LABS_EINVAL, "labs_enum_skew_min: NULL result");
+    if (L < 3 || L > 125 || (L % 2) == 0)
+        return fail(LABS_EINVAL, "labs_enum_skew_min: L = %d must be odd in [3, 125]", L);
+    const int n = (L + 1) / 2;
+    const uint64_t groups = 1ull << (n - 2);
+    if (r_begin > r_end || r_end > groups)
+        return fail(LABS_EINVAL, "labs_enum_skew_min: block [%llu, %llu) outside [0, 2^%d)",
+                    (unsigned long long)r_begin, (unsigned long long)r_end, n - 2);
+    memset(out, 0, sizeof *out);
+    out->min_isl = -1;
+    if (r_begin == r_end)
+        return LABS_OK;
+    int rc = check_device();
+    if (rc)
+        return rc;
+    const int blocks = enum_min_blocks(L);
+    if (blocks <= 0)
+        return fail(LABS_EDEVICE, "labs_enum_skew_min: occupancy query failed");
+    hipStream_t s = (hipStream_t)stream;
+    // launches of at most 2^32 groups and at most 2^20 passes per lane, so that per-wave counts
+    // stay far below 2^31 inside a launch
+    const uint64_t cap = std::min<uint64_t>(1ull << 32, (uint64_t)blocks * 256ull * 4ull * (1ull << 20));
+    EnumPartial *part = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    EnumPartial res{};
+    float ms = 0.0f;
+    hipError_t e = hipMalloc(&part, sizeof(EnumPartial) * (size_t)(blocks + 1));
+    if (e == hipSuccess) e = hipEventCreate(&ev0);
+    if (e == hipSuccess) e = hipEventCreate(&ev1);
+    if (e == hipSuccess) e = launch_enum_part_init(part, blocks, s);
+    if (e == hipSuccess) e = hipEventRecord(ev0, s);
+    for (uint64_t r = r_begin; e == hipSuccess && r < r_end;) {
+        const uint64_t cnt = std::min<uint64_t>(r_end - r, cap);
+        e = launch_enum_min(L, r, cnt, part, blocks, s);
+        r += cnt;
+    }
+    if (e == hipSuccess) e = launch_enum_final(part, blocks, part + blocks, s);
+    if (e == hipSuccess) e = hipEventRecord(ev1, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&res, part + blocks, sizeof res, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    if (part) (void)hipFree(part);
+    if (e != hipSuccess)
+        return hip_fail(e, "labs_enum_skew_min");
+    out->min_isl = res.min_isl == 0xFFFFFFFFu ? -1 : (int32_t)res.min_isl;
+    out->count = res.count;
+    out->first_x = res.min_isl == 0xFFFFFFFFu ? 0 : res.first_x;
+    out->states = 4 * (r_end - r_begin);
+    out->kernel_ms = (double)ms;
+    return LABS_OK;
+}
+
 extern "C" int labs_flip_scores_dev(int32_t L, int32_t count, const uint32_t *x_dev, int32_t *scores_dev,
                                     int32_t variant, void *stream)
 {
@@ -562,7 +620,8 @@ static std::string cache_path()
     return std::string(home ? home : "/tmp") + "/.cache/liblabs_autotune.txt";
 }
 
-// cache lines: "<arch> <L> <variant> <waves_per_block> <probe_width> <persistent>"
+// cache lines: "<arch> <L> <variant> <waves_per_block> <probe_width> <persistent>".  Later entries
+// win; an entry for L itself wins over the nearest L tuned for the same kernel shape.
 static bool cache_lookup(int L, labs_plan_opts *o)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -570,20 +629,26 @@ static bool cache_lookup(int L, labs_plan_opts *o)
     if (!f)
         return false;
     const std::string arch = device_arch();
-    std::string line;
+    const int shape = shape_for_length(L);
     bool found = false;
+    int best_dist = 1 << 30;
+    std::string line;
     while (std::getline(f, line)) {
         std::istringstream is(line);
         std::string a;
         int l, v, wpb, pw, pers;
         if (!(is >> a >> l >> v >> wpb >> pw >> pers))
             continue;
-        if (a == arch && l == L) {
+        if (a != arch || l < 3 || l > LABS_WALK_L_MAX || (l % 2) == 0 || shape_for_length(l) != shape)
+            continue;
+        const int dist = l > L ? l - L : L - l;
+        if (dist <= best_dist) {
+            best_dist = dist;
             o->variant = v;
             o->waves_per_block = wpb;
             o->probe_width = pw;
             o->persistent = pers;
-            found = true; // last entry wins
+            found = true;
         }
     }
     return found;

@@ -79,4 +79,17 @@ hipError_t launch_isl_batch(int L, int count, const int8_t *s, int64_t *isl, dou
                             int32_t *psl, int32_t *corr, hipStream_t stream);
 hipError_t launch_enum_skew(int L, int32_t *isl, hipStream_t stream);
 
+// Running result of one grouped skew-space minimum (one slot per block, then one final slot).
+struct EnumPartial {
+    uint32_t min_isl; // 0xFFFFFFFF: nothing covered yet
+    uint32_t reserved;
+    uint64_t count;
+    uint64_t first_x;
+};
+int enum_min_blocks(int L);
+hipError_t launch_enum_part_init(EnumPartial *part, int count, hipStream_t stream);
+hipError_t launch_enum_min(int L, uint64_t r_begin, uint64_t r_count, EnumPartial *part, int blocks,
+                           hipStream_t stream);
+hipError_t launch_enum_final(const EnumPartial *part, int count, EnumPartial *out, hipStream_t stream);
+
 } // namespace liblabs
