@@ -27,7 +27,9 @@
  * Parity unpinned: ref_start_bits, ref_zobrist and the visited-table, tie and restart rules of
  * ref_walk are readings of what the paper leaves open; they are checked only for internal
  * consistency (incremental walk == recomputing walk, bounded table == exact set before any
- * eviction, no revisits, best == first minimum of the trajectory).
+ * eviction, no revisits, best == first minimum of the trajectory).  So are the queue order,
+ * capacity and discard rules of ref_pq_walk: it is checked against ref_walk (capacity 1) and
+ * against an independent Python statement of the same reading.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -670,5 +672,224 @@ int ref_enum_skew_min(int32_t L, uint64_t r_begin, uint64_t r_end, int64_t *min_
     *min_isl = best;
     *count = cnt;
     *first_x = best < 0 ? 0 : first;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------
+ * Best-first search with a bounded priority queue: Algorithm 1 taken literally (Section 3).
+ * Each iteration flips every free symbol of the current state S in index order.  A flipped
+ * state found in the optional second table of evaluated neighbours (the xLastovka variant
+ * described in Section 3, which impxLast drops) is skipped without evaluation; every other one
+ * counts one function evaluation and, if it is not in the visited table HT, is recorded in the
+ * second table when that is in use, offered to the queue and compared with the best.  Then the front of the
+ * queue is removed and becomes S, and S is recorded in HT.
+ * Readings of what the paper leaves open:
+ *   - queue order: ascending (ISL, iteration that generated the entry, flip index), so equal
+ *     ISLs are served oldest first; capacity Q (the paper does not state it).  An entry offered
+ *     to a full queue replaces the queue's last entry if it precedes it, otherwise it is dropped.
+ *     Entries are not de-duplicated; a removed front entry whose state is already in HT is
+ *     discarded and the next one is taken.
+ *   - an empty queue (nothing left to take) restarts the search (a trap, counted like a
+ *     restart); restarts clear HT, the second table and the queue.
+ *   - best: strict improvement, checked when a neighbour is evaluated; best_step is the
+ *     iteration count after the iteration that evaluated it.  hit_step / watch_step: the first
+ *     iteration count after which the best ISL is <= target_isl / watch_isl (0 for the start).
+ *   - flip_evals: n per iteration, less the neighbours skipped by the second table (a
+ *     neighbour in HT counts, as in ref_walk).  A neighbour in HT is not recorded in the
+ *     second table.
+ *   - trace per iteration: (j when the new S is the current state's flip-j neighbour, -2 when it
+ *     is an older queue entry, -1 on a trap restart; ISL of the new S).
+ * With Q = 1 and no second table the queue holds exactly the best unvisited neighbour of the
+ * current state after each iteration, so the search coincides with ref_walk.
+ * The second table uses the visited table's layout and hash (own size nbr_log2; 0 = absent).
+ * ---------------------------------------------------------------------------------------- */
+typedef struct {
+    int64_t isl;
+    int64_t gen; /* iteration that generated the entry */
+    int32_t j;   /* flip of the generating state */
+    uint64_t x[ORACLE_MAX_WORDS];
+} pq_entry;
+
+static int pq_before(const pq_entry *a, const pq_entry *b)
+{
+    if (a->isl != b->isl)
+        return a->isl < b->isl;
+    if (a->gen != b->gen)
+        return a->gen < b->gen;
+    return a->j < b->j;
+}
+
+int ref_pq_walk(const ref_walk_cfg *cfg, int32_t capacity, int32_t nbr_log2, ref_walk_result *res,
+                int32_t *trace, int32_t *score_trace)
+{
+    const int32_t L = cfg->L;
+    if (L < 3 || (L % 2) == 0 || cfg->steps < 0 || cfg->table_log2 < 1 || cfg->table_log2 > 30 ||
+        capacity < 1 || nbr_log2 < 0 || nbr_log2 > 30)
+        return -1;
+    const int32_t n = (L + 1) / 2;
+    const int32_t nwords = (n + 63) / 64;
+    if (nwords > ORACLE_MAX_WORDS)
+        return -1;
+
+    int8_t *s = (int8_t *)malloc((size_t)L);
+    int64_t *C = (int64_t *)malloc(sizeof(int64_t) * (size_t)L);
+    uint64_t *z = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    pq_entry *Q = (pq_entry *)malloc(sizeof(pq_entry) * (size_t)capacity);
+    int32_t q = 0;
+    uint64_t x[ORACLE_MAX_WORDS], xn[ORACLE_MAX_WORDS];
+    memset(x, 0, sizeof x);
+    memset(xn, 0, sizeof xn);
+    for (int32_t j = 0; j < n; j++)
+        z[j] = ref_zobrist(j);
+
+    bounded_table B, N;
+    B.log2 = cfg->table_log2;
+    B.exact = (n <= cfg->table_log2);
+    B.T = (uint64_t *)calloc((size_t)1 << B.log2, sizeof(uint64_t));
+    N.log2 = nbr_log2;
+    N.exact = nbr_log2 > 0 && (n <= nbr_log2);
+    N.T = nbr_log2 > 0 ? (uint64_t *)calloc((size_t)1 << nbr_log2, sizeof(uint64_t)) : NULL;
+
+    int64_t isl = 0;
+    uint64_t h = 0;
+    uint32_t restart = 0;
+
+    memset(res, 0, sizeof *res);
+    res->hit_step = -1;
+    res->watch_step = -1;
+
+#define PQ_START()                                                                             \
+    do {                                                                                       \
+        ref_start_bits(L, cfg->seed, cfg->walk_id, restart, x, nwords);                        \
+        ref_skew_expand(L, x, s);                                                              \
+        isl = ref_isl(L, s);                                                                   \
+        h = 0;                                                                                 \
+        for (int32_t j = 0; j < n; j++)                                                        \
+            if ((x[j / 64] >> (j % 64)) & 1u)                                                  \
+                h ^= z[j];                                                                     \
+        memset(B.T, 0, sizeof(uint64_t) * ((size_t)1 << B.log2));                              \
+        B.T[table_slot(&B, h, x)] = h | 1u;                                                    \
+        if (N.T)                                                                               \
+            memset(N.T, 0, sizeof(uint64_t) * ((size_t)1 << N.log2));                          \
+        q = 0;                                                                                 \
+    } while (0)
+
+    PQ_START();
+    res->best_isl = isl;
+    res->best_step = 0;
+    to_u32_words(x, nwords, res->best_bits);
+    if (cfg->target_isl >= 0 && isl <= cfg->target_isl)
+        res->hit_step = 0;
+    if (cfg->watch_isl >= 0 && isl <= cfg->watch_isl)
+        res->watch_step = 0;
+
+    int64_t t = 0, flips = 0;
+    while (t < cfg->steps && !(cfg->target_isl >= 0 && res->hit_step >= 0)) {
+        /* search the neighbourhood (scores by the pinned one-flip evaluation) */
+        ref_corr(L, s, C);
+        for (int32_t j = 0; j < n; j++) {
+            memcpy(xn, x, sizeof x);
+            xn[j / 64] ^= (uint64_t)1 << (j % 64);
+            const uint64_t hn = h ^ z[j];
+            const int64_t v = ref_flip_isl_incr(L, s, C, j);
+            if (score_trace)
+                score_trace[t * n + j] = (int32_t)v;
+            if (N.T && N.T[table_slot(&N, hn, xn)] == (hn | 1u))
+                continue;
+            flips++;
+            if (B.T[table_slot(&B, hn, xn)] == (hn | 1u))
+                continue;
+            if (N.T)
+                N.T[table_slot(&N, hn, xn)] = hn | 1u;
+            pq_entry e;
+            e.isl = v;
+            e.gen = t;
+            e.j = j;
+            memcpy(e.x, xn, sizeof e.x);
+            if (q < capacity) {
+                Q[q++] = e;
+            } else {
+                int32_t w = 0;
+                for (int32_t i = 1; i < q; i++)
+                    if (pq_before(&Q[w], &Q[i]))
+                        w = i;
+                if (pq_before(&e, &Q[w]))
+                    Q[w] = e;
+            }
+            if (v < res->best_isl) {
+                res->best_isl = v;
+                res->best_step = t + 1;
+                to_u32_words(xn, nwords, res->best_bits);
+            }
+        }
+        /* take the front of the queue, skipping states visited since they were queued */
+        int found = 0;
+        pq_entry f;
+        while (q > 0) {
+            int32_t b = 0;
+            for (int32_t i = 1; i < q; i++)
+                if (pq_before(&Q[i], &Q[b]))
+                    b = i;
+            f = Q[b];
+            Q[b] = Q[--q];
+            uint64_t hf = 0;
+            for (int32_t j = 0; j < n; j++)
+                if ((f.x[j / 64] >> (j % 64)) & 1u)
+                    hf ^= z[j];
+            if (B.T[table_slot(&B, hf, f.x)] == (hf | 1u))
+                continue;
+            found = 1;
+            break;
+        }
+        int32_t move;
+        if (!found) {
+            res->traps++;
+            res->restarts++;
+            restart++;
+            PQ_START();
+            move = -1;
+        } else {
+            move = (f.gen == t) ? f.j : -2;
+            memcpy(x, f.x, sizeof x);
+            ref_skew_expand(L, x, s);
+            isl = ref_isl(L, s);
+            if (isl != f.isl) {
+                free(s); free(C); free(z); free(Q); free(B.T); free(N.T);
+                return -2;
+            }
+            h = 0;
+            for (int32_t j = 0; j < n; j++)
+                if ((x[j / 64] >> (j % 64)) & 1u)
+                    h ^= z[j];
+            B.T[table_slot(&B, h, x)] = h | 1u;
+        }
+        t++;
+        if (trace) {
+            trace[2 * t - 2] = move;
+            trace[2 * t - 1] = (int32_t)isl;
+        }
+        if (cfg->target_isl >= 0 && res->hit_step < 0 && res->best_isl <= cfg->target_isl)
+            res->hit_step = t;
+        if (cfg->watch_isl >= 0 && res->watch_step < 0 && res->best_isl <= cfg->watch_isl)
+            res->watch_step = t;
+        if (found && cfg->restart_period > 0 && t % cfg->restart_period == 0 && t < cfg->steps &&
+            !(cfg->target_isl >= 0 && res->hit_step >= 0)) {
+            res->restarts++;
+            restart++;
+            PQ_START();
+        }
+    }
+#undef PQ_START
+
+    res->steps_done = t;
+    res->flip_evals = flips;
+    res->final_isl = isl;
+    to_u32_words(x, nwords, res->final_bits);
+    free(s);
+    free(C);
+    free(z);
+    free(Q);
+    free(B.T);
+    free(N.T);
     return 0;
 }

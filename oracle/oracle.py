@@ -65,6 +65,9 @@ def lib():
     L.ref_zobrist.restype = ctypes.c_uint64
     L.ref_walk.argtypes = [ctypes.POINTER(WalkCfg), ctypes.POINTER(WalkResult), i32p, i32p]
     L.ref_walk.restype = ctypes.c_int
+    L.ref_pq_walk.argtypes = [ctypes.POINTER(WalkCfg), ctypes.c_int32, ctypes.c_int32,
+                              ctypes.POINTER(WalkResult), i32p, i32p]
+    L.ref_pq_walk.restype = ctypes.c_int
     L.ref_enum_skew.argtypes = [ctypes.c_int32, i64p]
     L.ref_enum_skew.restype = ctypes.c_int
     L.ref_enum_skew_min.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64, i64p, u64p, u64p]
@@ -220,8 +223,11 @@ def zobrist(j: int) -> int:
 # --- the walk --------------------------------------------------------------------------------
 
 def walk(L, seed, walk_id=0, steps=1000, table_log2=16, restart_period=0, target_isl=-1,
-         watch_isl=-1, brute=False, ideal=False, trace=False, score_trace=False):
-    """Runs one walk; returns a dict of results (+ 'trace' (steps,2) / 'scores' (steps,n))."""
+         watch_isl=-1, brute=False, ideal=False, trace=False, score_trace=False, pq_capacity=0,
+         nbr_table_log2=0):
+    """Runs one walk; returns a dict of results (+ 'trace' (steps,2) / 'scores' (steps,n)).
+    pq_capacity > 0 runs the best-first search with a queue of that capacity instead (and
+    nbr_table_log2 > 0 adds the second table of evaluated neighbours)."""
     n = (L + 1) // 2
     cfg = WalkCfg(L, table_log2, seed & 0xFFFFFFFFFFFFFFFF, walk_id,
                   (BRUTE if brute else 0) | (IDEAL if ideal else 0),
@@ -230,11 +236,12 @@ def walk(L, seed, walk_id=0, steps=1000, table_log2=16, restart_period=0, target
     tr = np.zeros((max(steps, 1), 2), dtype=np.int32) if trace else None
     sc = np.zeros((max(steps, 1), n), dtype=np.int32) if score_trace else None
     i32p = ctypes.POINTER(ctypes.c_int32)
-    rc = lib().ref_walk(
-        ctypes.byref(cfg), ctypes.byref(res),
-        tr.ctypes.data_as(i32p) if tr is not None else None,
-        sc.ctypes.data_as(i32p) if sc is not None else None,
-    )
+    trp = tr.ctypes.data_as(i32p) if tr is not None else None
+    scp = sc.ctypes.data_as(i32p) if sc is not None else None
+    if pq_capacity > 0:
+        rc = lib().ref_pq_walk(ctypes.byref(cfg), pq_capacity, nbr_table_log2, ctypes.byref(res), trp, scp)
+    else:
+        rc = lib().ref_walk(ctypes.byref(cfg), ctypes.byref(res), trp, scp)
     if rc != 0:
         raise RuntimeError(f"ref_walk failed ({rc})")
     out = {
