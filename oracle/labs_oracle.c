@@ -679,7 +679,8 @@ int ref_enum_skew_min(int32_t L, uint64_t r_begin, uint64_t r_end, int64_t *min_
  * Best-first search with a bounded priority queue: Algorithm 1 taken literally (Section 3).
  * Each iteration flips every free symbol of the current state S in index order.  A flipped
  * state found in the optional second table of evaluated neighbours (the xLastovka variant
- * described in Section 3, which impxLast drops) is skipped without evaluation; every other one
+ * described in Section 3, which impxLast drops), as that table stood before the iteration, is
+ * skipped without evaluation; every other one
  * counts one function evaluation and, if it is not in the visited table HT, is recorded in the
  * second table when that is in use, offered to the queue and compared with the best.  Then the front of the
  * queue is removed and becomes S, and S is recorded in HT.
@@ -735,6 +736,7 @@ int ref_pq_walk(const ref_walk_cfg *cfg, int32_t capacity, int32_t nbr_log2, ref
     int64_t *C = (int64_t *)malloc(sizeof(int64_t) * (size_t)L);
     uint64_t *z = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
     pq_entry *Q = (pq_entry *)malloc(sizeof(pq_entry) * (size_t)capacity);
+    uint8_t *nbr_seen = (uint8_t *)malloc((size_t)n);
     int32_t q = 0;
     uint64_t x[ORACLE_MAX_WORDS], xn[ORACLE_MAX_WORDS];
     memset(x, 0, sizeof x);
@@ -785,8 +787,15 @@ int ref_pq_walk(const ref_walk_cfg *cfg, int32_t capacity, int32_t nbr_log2, ref
 
     int64_t t = 0, flips = 0;
     while (t < cfg->steps && !(cfg->target_isl >= 0 && res->hit_step >= 0)) {
-        /* search the neighbourhood (scores by the pinned one-flip evaluation) */
+        /* search the neighbourhood (scores by the pinned one-flip evaluation); the second table
+         * is consulted as it stood before this iteration */
         ref_corr(L, s, C);
+        for (int32_t j = 0; j < n; j++) {
+            memcpy(xn, x, sizeof x);
+            xn[j / 64] ^= (uint64_t)1 << (j % 64);
+            const uint64_t hn = h ^ z[j];
+            nbr_seen[j] = N.T && N.T[table_slot(&N, hn, xn)] == (hn | 1u);
+        }
         for (int32_t j = 0; j < n; j++) {
             memcpy(xn, x, sizeof x);
             xn[j / 64] ^= (uint64_t)1 << (j % 64);
@@ -794,7 +803,7 @@ int ref_pq_walk(const ref_walk_cfg *cfg, int32_t capacity, int32_t nbr_log2, ref
             const int64_t v = ref_flip_isl_incr(L, s, C, j);
             if (score_trace)
                 score_trace[t * n + j] = (int32_t)v;
-            if (N.T && N.T[table_slot(&N, hn, xn)] == (hn | 1u))
+            if (nbr_seen[j])
                 continue;
             flips++;
             if (B.T[table_slot(&B, hn, xn)] == (hn | 1u))
@@ -854,7 +863,7 @@ int ref_pq_walk(const ref_walk_cfg *cfg, int32_t capacity, int32_t nbr_log2, ref
             ref_skew_expand(L, x, s);
             isl = ref_isl(L, s);
             if (isl != f.isl) {
-                free(s); free(C); free(z); free(Q); free(B.T); free(N.T);
+                free(s); free(C); free(z); free(Q); free(nbr_seen); free(B.T); free(N.T);
                 return -2;
             }
             h = 0;
@@ -889,6 +898,7 @@ int ref_pq_walk(const ref_walk_cfg *cfg, int32_t capacity, int32_t nbr_log2, ref
     free(C);
     free(z);
     free(Q);
+    free(nbr_seen);
     free(B.T);
     free(N.T);
     return 0;

@@ -39,24 +39,55 @@ def _isl_np(L, x):
     return int(sum(int(np.dot(s[: L - k], s[k:])) ** 2 for k in range(1, L)))
 
 
-def _python_best_first(L, seed, walk_id, steps, Q, nbr):
-    """The reading of Algorithm 1 stated independently: exact sets, list queue."""
+class _Bounded:
+    """The second table as a bounded direct-mapped table: slot = top `log2` bits of the Zobrist
+    hash, stored word = hash | 1, a record overwrites."""
+
+    def __init__(self, n, log2):
+        self.z = [o.zobrist(j) for j in range(n)]
+        self.log2 = log2
+        self.T = {}
+
+    def h(self, x):
+        v = 0
+        for j, zj in enumerate(self.z):
+            if (x >> j) & 1:
+                v ^= zj
+        return v
+
+    def __contains__(self, x):
+        hx = self.h(x)
+        return self.T.get(hx >> (64 - self.log2)) == (hx | 1)
+
+    def add(self, x):
+        hx = self.h(x)
+        self.T[hx >> (64 - self.log2)] = hx | 1
+
+
+def _python_best_first(L, seed, walk_id, steps, Q, nbr, nbr_log2=None):
+    """The reading of Algorithm 1 stated independently: exact visited set, list queue, and the
+    second table exact (nbr_log2 None) or bounded."""
     n = (L + 1) // 2
     restart = 0
+
+    def new_n2():
+        return set() if nbr_log2 is None else _Bounded(n, nbr_log2)
+
 
     def start():
         return o.start_bits(L, seed, walk_id, restart)
 
     x = start()
     isl = _isl_np(L, x)
-    HT, N2, queue = {x}, set(), []
+    HT, N2, queue = {x}, new_n2(), []
     best, best_step, best_x = isl, 0, x
     flips = traps = 0
     trace = []
     for t in range(steps):
+        seen = [nbr and (x ^ (1 << j)) in N2 for j in range(n)]
         for j in range(n):
             xn = x ^ (1 << j)
-            if nbr and xn in N2:
+            if seen[j]:
                 continue
             flips += 1
             if xn in HT:
@@ -85,7 +116,7 @@ def _python_best_first(L, seed, walk_id, steps, Q, nbr):
             restart += 1
             x = start()
             isl = _isl_np(L, x)
-            HT, N2, queue = {x}, set(), []
+            HT, N2, queue = {x}, new_n2(), []
             trace.append((-1, isl))
             continue
         x, isl = f[3], f[0]
@@ -103,6 +134,18 @@ def test_matches_independent_statement(L, Q, nbr):
     want = _python_best_first(L, 5, 1, steps, Q, nbr)
     got = o.walk(L, 5, 1, steps=steps, table_log2=n + 1, pq_capacity=Q, nbr_table_log2=(n + 1) if nbr else 0,
                  trace=True)
+    for k in ("best_isl", "best_step", "best_bits", "final_bits", "final_isl", "flip_evals", "traps"):
+        assert got[k] == want[k], (k, got[k], want[k])
+    assert np.array_equal(got["trace"], want["trace"])
+
+
+@pytest.mark.parametrize("L,Q,nlog2", [(21, 8, 3), (25, 4, 5), (31, 16, 6)])
+def test_bounded_second_table_matches_independent_statement(L, Q, nlog2):
+    # a second table far smaller than the neighbourhood: slot collisions between neighbours of
+    # one state are frequent, so the look-up-before-recording and last-index-wins rules matter
+    steps = 150
+    want = _python_best_first(L, 9, 2, steps, Q, True, nbr_log2=nlog2)
+    got = o.walk(L, 9, 2, steps=steps, table_log2=(L + 3) // 2, pq_capacity=Q, nbr_table_log2=nlog2, trace=True)
     for k in ("best_isl", "best_step", "best_bits", "final_bits", "final_isl", "flip_evals", "traps"):
         assert got[k] == want[k], (k, got[k], want[k])
     assert np.array_equal(got["trace"], want["trace"])
