@@ -9,7 +9,9 @@ every walk to its start state and runs the job to completion on the GPU.
 Printed: one JSON line with the throughput in flip evaluations per second (the paper's speed
 unit, Section 3: one evaluated flip = one function evaluation), the roofline of the walk kernel,
 the oracle timed on the host cores on a bounded sample of the same workload, the plain
-one-walk-per-launch form on a sample, and time-to-F >= 8 statistics.
+one-walk-per-launch form on a sample, and time-to-F >= 8 statistics; then (unless --no-extras)
+an uneven batch of all 52 lengths, the serving workload, the exhaustive skew minimum at L = 61
+and 69, and the best-first search with a bounded queue (with and without the second table).
 """
 import argparse
 import hashlib
@@ -182,6 +184,27 @@ def uneven_batch(labs):
             / (ms / 1000.0) / (VALU_PEAK_TOPS * 1e12)}
 
 
+def best_first(labs, walks=WALKS, steps=1000):
+    """Algorithm 1 taken literally: best-first search with a queue of 64 entries per search
+    (impxLast), and with the second table of evaluated neighbours as well (xLastovka), at the
+    headline length; flip evaluations per second, and the merit factors reached."""
+    import numpy as np
+
+    cfg = [labs.make_cfg(L, SEED, w, steps=steps, table_log2=TABLE_LOG2) for w in range(walks)]
+    labs.pq_walk_batch(cfg[:256], 64)  # warm the launch path
+    out = {"L": L, "searches": walks, "iterations": steps, "capacity": 64}
+    for name, nlog2 in (("impxLast", 0), ("xLastovka", TABLE_LOG2)):
+        res, ms = labs.pq_walk_batch(cfg, 64, nlog2)
+        evals = sum(r["flip_evals"] for r in res)
+        best = np.array([r["best_isl"] for r in res], dtype=np.float64)
+        out[name] = {"nbr_table_log2": nlog2, "kernel_ms": ms, "flip_evals": evals,
+                     "flip_evals_per_s": evals / (ms / 1000.0),
+                     "alg_ops_frac_of_valu_peak": steps * walks * N * ALG_OPS_PER_FLIP / (ms / 1000.0)
+                     / (VALU_PEAK_TOPS * 1e12),
+                     "mean_best_F": float(np.mean(L * L / (2.0 * best))), "max_best_F": float(L * L / (2.0 * best.min()))}
+    return out
+
+
 def enum_alg_ops_per_group(Lx):
     """Word operations to score one sequence with the bit-packed form of Eq. (1)-(2): for each even
     lag k, per 32-bit word of the L - k overlapping positions a funnel shift, a masked xor and a
@@ -232,7 +255,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the serving, uneven-batch and enumeration measurements")
+                    help="skip the serving, uneven-batch, enumeration and best-first measurements")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -319,6 +342,7 @@ def main():
         line["uneven_batch"] = uneven_batch(labs)
         line["serving"] = serving(labs)
         line["enumeration"] = enumeration(labs)
+        line["best_first"] = best_first(labs)
     if not args.no_cpu:
         line["cpu_baseline"], _ = cpu_baseline()
     print(json.dumps(line), flush=True)

@@ -198,6 +198,41 @@ typedef struct labs_plan_opts {
 int labs_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, labs_walk_result *out,
                     int32_t *trace, int32_t *scores, void *stream);
 
+/* ---------------------------------------------------------------------------------------------
+ * Best-first search with a bounded priority queue: Algorithm 1 taken literally (Section 3), and
+ * optionally with the second table of evaluated neighbours of xLastovka (Section 3).  Each
+ * iteration scores the n flips of the current state S; a neighbour found in the second table (as
+ * it stood before the iteration) is skipped without evaluation; a neighbour in the visited table
+ * is evaluated but skipped; every other neighbour is recorded in the second table (when in use;
+ * of several neighbours sharing a slot the highest flip index is stored), offered to the queue
+ * and compared with the best.  Then the front entry whose state is not visited becomes S and is
+ * recorded as visited; an empty queue restarts the search (a trap).  The queue is ordered by
+ * (ISL, iteration that generated the entry, flip index); an entry offered to a full queue
+ * replaces the last entry if it precedes it, else it is dropped; entries are not de-duplicated.
+ * Start states, tables, restarts, target and watch are those of the walk above, except:
+ *   - best, hit_step and watch_step are taken when a neighbour is evaluated: best_step (and
+ *     hit / watch) is the iteration count after the iteration that evaluated the state;
+ *   - flip_evals counts n per iteration less the neighbours skipped by the second table;
+ *   - trace records (j when the new S is the current state's flip-j neighbour, -2 when it is an
+ *     older queue entry, -1 on a trap; ISL of the new S);
+ *   - restarts clear the visited table, the second table and the queue.
+ * With capacity 1 and no second table the search is exactly the walk of labs_walk_batch.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct labs_pq_opts {
+    int32_t capacity;       /* queue entries per walk, 1..64 */
+    int32_t nbr_table_log2; /* 0 = no second table (impxLast); else 1..30: 2^log2 words per walk,
+                               the visited table's layout and hash */
+} labs_pq_opts;
+
+/* Runs n_walks best-first searches to completion (one launch per kernel shape; steps < 2^31 per
+ * walk) and copies the results to out (host).  trace / scores as for labs_walk_batch.
+ * kernel_ms (may be NULL): device time of the search launches.  Synchronous on stream.
+ * Allocates and frees its device state (visited and second tables: n_walks * (2^table_log2 +
+ * 2^nbr_table_log2) * 8 bytes; LABS_ENOMEM if that does not fit). */
+int labs_pq_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, const labs_pq_opts *opts,
+                       labs_walk_result *out, int32_t *trace, int32_t *scores, double *kernel_ms,
+                       void *stream);
+
 typedef struct labs_walk_plan labs_walk_plan;
 
 /* Allocates device state for n_walks walks (visited tables: n_walks * 2^table_log2 * 8 bytes;

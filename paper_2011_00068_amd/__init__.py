@@ -45,7 +45,7 @@ EXPORTS = [
     "labs_flip_scores_dev",
     "labs_walk_batch", "labs_walk_plan_create", "labs_walk_plan_run", "labs_walk_plan_results",
     "labs_walk_plan_get_opts", "labs_walk_plan_last_timing", "labs_walk_plan_destroy",
-    "labs_autotune",
+    "labs_autotune", "labs_pq_walk_batch",
     "labs_server_create", "labs_search_submit", "labs_search_poll", "labs_search_wait",
     "labs_search_cancel", "labs_server_stats", "labs_server_destroy",
 ]
@@ -114,6 +114,10 @@ class EnumMinResult(ctypes.Structure):
         ("states", ctypes.c_uint64),
         ("kernel_ms", ctypes.c_double),
     ]
+
+
+class PqOpts(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_int32), ("nbr_table_log2", ctypes.c_int32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -192,6 +196,8 @@ def lib():
     L.labs_walk_plan_destroy.argtypes = [vp]
     L.labs_walk_plan_destroy.restype = None
     L.labs_autotune.argtypes = [i32, i32, P(PlanOpts)]
+    L.labs_pq_walk_batch.argtypes = [i32, P(WalkCfg), P(PqOpts), P(WalkResult), vp, vp,
+                                     P(ctypes.c_double), vp]
     L.labs_server_create.argtypes = [P(ServerOpts), P(vp)]
     L.labs_search_submit.argtypes = [vp, P(SearchReq), P(u64)]
     L.labs_search_poll.argtypes = [vp, u64, P(SearchStatus)]
@@ -422,6 +428,31 @@ def walk_batch(cfgs, stream=None):
         if scores[i] is not None:
             out[i]["scores"] = scores[i]
     return out
+
+
+def pq_walk_batch(cfgs, capacity, nbr_table_log2=0, stream=None):
+    """labs_pq_walk_batch: best-first searches with a bounded queue (and optionally the second
+    table); returns (result dicts with traces if asked, device milliseconds)."""
+    cfgs = list(cfgs)
+    arr = (WalkCfg * len(cfgs))(*cfgs)
+    res = (WalkResult * len(cfgs))()
+    tr = sum(c.steps for c in cfgs if c.flags & TRACE)
+    sc = sum(c.steps * ((c.L + 1) // 2) for c in cfgs if c.flags & TRACE_SCORES)
+    tbuf = ctypes.create_string_buffer(8 * tr) if tr else None
+    sbuf = ctypes.create_string_buffer(4 * sc) if sc else None
+    ms = ctypes.c_double()
+    s = _stream() if stream is None else ctypes.c_void_p(stream)
+    opts = PqOpts(capacity, nbr_table_log2)
+    _check(lib().labs_pq_walk_batch(len(cfgs), arr, ctypes.byref(opts), res, tbuf, sbuf, ctypes.byref(ms), s),
+           "labs_pq_walk_batch")
+    out = [_result_dict(res[i], (cfgs[i].L + 1) // 2) for i in range(len(cfgs))]
+    traces, scores = _split_traces(cfgs, tbuf.raw if tbuf else b"", sbuf.raw if sbuf else b"")
+    for i in range(len(cfgs)):
+        if traces[i] is not None:
+            out[i]["trace"] = traces[i]
+        if scores[i] is not None:
+            out[i]["scores"] = scores[i]
+    return out, ms.value
 
 
 def autotune(L, n_walks):

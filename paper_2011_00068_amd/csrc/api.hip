@@ -604,6 +604,134 @@ extern "C" int labs_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, labs_w
     return rc;
 }
 
+extern "C" int labs_pq_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, const labs_pq_opts *opts,
+                                  labs_walk_result *out, int32_t *trace, int32_t *scores, double *kernel_ms,
+                                  void *stream)
+{
+    if (n_walks < 1 || !cfg || !opts || !out)
+        return fail(LABS_EINVAL, "labs_pq_walk_batch: n_walks = %d with cfg, opts and out required", n_walks);
+    if (opts->capacity < 1 || opts->capacity > 64)
+        return fail(LABS_EINVAL, "labs_pq_walk_batch: capacity = %d must be in [1, 64]", opts->capacity);
+    if (opts->nbr_table_log2 < 0 || opts->nbr_table_log2 > 30)
+        return fail(LABS_EINVAL, "labs_pq_walk_batch: nbr_table_log2 = %d must be in [0, 30]", opts->nbr_table_log2);
+    for (int32_t i = 0; i < n_walks; i++) {
+        int rc = walk_cfg_check(cfg[i], i);
+        if (rc)
+            return rc;
+        if (cfg[i].steps >= ((int64_t)1 << 31))
+            return fail(LABS_EINVAL, "labs_pq_walk_batch: walk %d: steps must be below 2^31", i);
+    }
+    int rc = check_device();
+    if (rc)
+        return rc;
+    const int nlog2 = opts->nbr_table_log2;
+    std::vector<WalkState> st((size_t)n_walks);
+    int64_t table_words = 0, trace_records = 0, score_entries = 0;
+    for (int32_t i = 0; i < n_walks; i++) {
+        const labs_walk_cfg &c = cfg[i];
+        WalkState &w = st[(size_t)i];
+        memset(&w, 0, sizeof w);
+        w.L = c.L;
+        w.table_log2 = c.table_log2;
+        w.seed = c.seed;
+        w.walk_id = c.walk_id;
+        w.flags = c.flags;
+        w.steps = c.steps;
+        w.restart_period = c.restart_period;
+        w.target_isl = c.target_isl;
+        w.watch_isl = c.watch_isl;
+        w.table_offset = table_words;
+        table_words += (int64_t)1 << c.table_log2;
+        w.trace_offset = (c.flags & LABS_TRACE) ? trace_records : -1;
+        if (c.flags & LABS_TRACE)
+            trace_records += c.steps;
+        w.score_offset = (c.flags & LABS_TRACE_SCORES) ? score_entries : -1;
+        if (c.flags & LABS_TRACE_SCORES)
+            score_entries += c.steps * ((c.L + 1) / 2);
+        w.step_cap = INT64_MAX;
+        w.hit_step = -1;
+        w.watch_step = -1;
+        w.status = kFresh;
+    }
+    // one launch per kernel shape, over the walks of that shape
+    std::vector<int32_t> order((size_t)n_walks);
+    std::vector<int32_t> first(9, 0);
+    {
+        std::vector<int32_t> count(8, 0);
+        for (int32_t i = 0; i < n_walks; i++)
+            count[(size_t)shape_for_length(cfg[i].L)]++;
+        for (int s = 0; s < 8; s++)
+            first[(size_t)s + 1] = first[(size_t)s] + count[(size_t)s];
+        std::vector<int32_t> fill(first.begin(), first.end() - 1);
+        for (int32_t i = 0; i < n_walks; i++)
+            order[(size_t)fill[(size_t)shape_for_length(cfg[i].L)]++] = i;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    WalkState *d_st = nullptr;
+    uint64_t *d_tables = nullptr, *d_nbr = nullptr;
+    int32_t *d_trace = nullptr, *d_scores = nullptr, *d_order = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    float ms = 0.0f;
+    hipError_t e = hipMalloc(&d_st, sizeof(WalkState) * (size_t)n_walks);
+    if (e == hipSuccess) e = hipMalloc(&d_tables, sizeof(uint64_t) * (size_t)table_words);
+    if (e == hipSuccess && nlog2 > 0) e = hipMalloc(&d_nbr, sizeof(uint64_t) * ((size_t)n_walks << nlog2));
+    if (e == hipSuccess && trace_records > 0) e = hipMalloc(&d_trace, sizeof(int32_t) * 2 * (size_t)trace_records);
+    if (e == hipSuccess && score_entries > 0) e = hipMalloc(&d_scores, sizeof(int32_t) * (size_t)score_entries);
+    if (e == hipSuccess) e = hipMalloc(&d_order, sizeof(int32_t) * (size_t)n_walks);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_st, st.data(), sizeof(WalkState) * (size_t)n_walks, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_order, order.data(), sizeof(int32_t) * (size_t)n_walks, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && d_trace) e = hipMemsetAsync(d_trace, 0, sizeof(int32_t) * 2 * (size_t)trace_records, s);
+    if (e == hipSuccess && d_scores) e = hipMemsetAsync(d_scores, 0, sizeof(int32_t) * (size_t)score_entries, s);
+    if (e == hipSuccess) e = hipEventCreate(&ev0);
+    if (e == hipSuccess) e = hipEventCreate(&ev1);
+    if (e == hipSuccess) e = hipEventRecord(ev0, s);
+    for (int sh = 7; e == hipSuccess && sh >= 0; sh--) {
+        const int32_t cnt = first[(size_t)sh + 1] - first[(size_t)sh];
+        if (cnt > 0)
+            e = launch_pq_walk(sh, d_st, cnt, d_order + first[(size_t)sh], d_tables, d_nbr, nlog2, opts->capacity,
+                               d_trace, d_scores, s);
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev1, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(st.data(), d_st, sizeof(WalkState) * (size_t)n_walks, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && trace && d_trace)
+        e = hipMemcpyAsync(trace, d_trace, sizeof(int32_t) * 2 * (size_t)trace_records, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && scores && d_scores)
+        e = hipMemcpyAsync(scores, d_scores, sizeof(int32_t) * (size_t)score_entries, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    if (d_st) (void)hipFree(d_st);
+    if (d_tables) (void)hipFree(d_tables);
+    if (d_nbr) (void)hipFree(d_nbr);
+    if (d_trace) (void)hipFree(d_trace);
+    if (d_scores) (void)hipFree(d_scores);
+    if (d_order) (void)hipFree(d_order);
+    if (e != hipSuccess)
+        return hip_fail(e, "labs_pq_walk_batch");
+    for (int32_t i = 0; i < n_walks; i++) {
+        const WalkState &w = st[(size_t)i];
+        labs_walk_result &r = out[i];
+        memset(&r, 0, sizeof r);
+        r.best_isl = w.best_isl;
+        r.best_step = w.best_step;
+        r.steps_done = w.t;
+        r.flip_evals = w.flips;
+        r.hit_step = w.hit_step;
+        r.watch_step = w.watch_step;
+        r.final_isl = w.isl;
+        r.restarts = w.restarts;
+        r.traps = w.traps;
+        for (int k = 0; k < kXWords; k++) {
+            r.best_bits[k] = w.best_x[k];
+            r.final_bits[k] = w.x[k];
+        }
+    }
+    if (kernel_ms)
+        *kernel_ms = (double)ms;
+    return LABS_OK;
+}
+
 // =============================================================================================
 // Option resolution and the autotuner.
 // =============================================================================================
