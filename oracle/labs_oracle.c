@@ -21,7 +21,7 @@
  *
  * Pins: Eq. (1)-(4), PSL, the hex codec and the one-flip evaluation are pinned by Table 1, the
  * Barker-13 worked case, numpy.correlate, brute force over all 2^L sequences and the plain
- * definition of a flipped ISL (tests/test_oracle_*.py); the grouped skew-space minimum by brute
+ * definition of a flipped ISL (tests/test_oracle_*.py), for skew-symmetric and general sequences; the grouped skew-space minimum by brute
  * force over all 2^L sequences and numpy on blocks up to n = 63; SplitMix64 by its published
  * first outputs.
  * Parity unpinned: ref_start_bits, ref_zobrist and the visited-table, tie and restart rules of
@@ -252,6 +252,33 @@ void ref_flip_scores(int32_t L, const uint64_t *x, int64_t *out, int brute)
     free(C);
 }
 
+/* One-flip evaluation for a general (not skew-symmetric) sequence: flip j negates s_j alone.
+ * Plain definition: recompute Eq. (1)-(2) for the flipped sequence. */
+int64_t ref_flip_isl_general_brute(int32_t L, const int8_t *s, int32_t j)
+{
+    int8_t *t = (int8_t *)malloc((size_t)L);
+    memcpy(t, s, (size_t)L);
+    t[j] = (int8_t)(-t[j]);
+    int64_t isl = ref_isl(L, t);
+    free(t);
+    return isl;
+}
+
+/* Incremental form (Eq. (1)): negating s_j negates the products s_j s_{j+k} and s_{j-k} s_j, so
+ *     dC_k = -2 s_j ( s_{j+k} [j+k <= L-1] + s_{j-k} [j-k >= 0] ),  k = 1 .. L-1,
+ * and the flipped ISL is sum_k (C_k + dC_k)^2 over every k (odd k included). */
+int64_t ref_flip_isl_general_incr(int32_t L, const int8_t *s, const int64_t *C, int32_t j)
+{
+    int64_t isl = 0;
+    for (int32_t k = 1; k <= L - 1; k++) {
+        int64_t p = (j + k <= L - 1) ? s[j + k] : 0;
+        int64_t q = (j - k >= 0) ? s[j - k] : 0;
+        int64_t v = C[k] - 2 * (int64_t)s[j] * (p + q);
+        isl += v * v;
+    }
+    return isl;
+}
+
 /* ------------------------------------------------------------------------------------------
  * Counter-based random numbers: SplitMix64 (G. L. Steele, D. Lea, C. H. Flood, "Fast
  * splittable pseudorandom number generators", OOPSLA 2014), written from its published
@@ -276,10 +303,9 @@ uint64_t ref_sm64_at(uint64_t seed, uint64_t i)
  * sequence"; the paper does not say how): free symbols i.i.d. uniform, drawn as 64-bit words
  *   key_w = sm64_at(seed, w), key_wr = sm64_at(key_w, r), word_i = sm64_at(key_wr, i),
  * bit j of x = bit (j % 64) of word_(j / 64), bits at j >= n cleared. */
-void ref_start_bits(int32_t L, uint64_t seed, uint32_t walk_id, uint32_t restart, uint64_t *x,
-                    int32_t nwords)
+static void draw_bits(int32_t n, uint64_t seed, uint32_t walk_id, uint32_t restart, uint64_t *x,
+                      int32_t nwords)
 {
-    int32_t n = (L + 1) / 2;
     uint64_t kw = ref_sm64_at(seed, walk_id);
     uint64_t kr = ref_sm64_at(kw, restart);
     for (int32_t w = 0; w < nwords; w++) {
@@ -293,6 +319,19 @@ void ref_start_bits(int32_t L, uint64_t seed, uint32_t walk_id, uint32_t restart
     }
 }
 
+void ref_start_bits(int32_t L, uint64_t seed, uint32_t walk_id, uint32_t restart, uint64_t *x,
+                    int32_t nwords)
+{
+    draw_bits((L + 1) / 2, seed, walk_id, restart, x, nwords);
+}
+
+/* Start sequence of a general walk (ORACLE_GENERAL): the same draw over all L symbols. */
+void ref_start_bits_general(int32_t L, uint64_t seed, uint32_t walk_id, uint32_t restart, uint64_t *x,
+                            int32_t nwords)
+{
+    draw_bits(L, seed, walk_id, restart, x, nwords);
+}
+
 /* Zobrist key of free symbol j (A. L. Zobrist, 1970): z_j = sm64_at(0x2011000068ABCDEF, j).
  * The hash of a state is the XOR of z_j over its set free bits. */
 uint64_t ref_zobrist(int32_t j)
@@ -304,6 +343,9 @@ uint64_t ref_zobrist(int32_t j)
  * The search walk (Section 3, Algorithm 1, in its self-avoiding-walk reading): at every step
  * score all n flips of the current state, move to the best flip whose resulting state has not
  * been visited (lowest index on ties), record it as visited, and keep the best state seen.
+ * With ORACLE_GENERAL the same walk runs over general sequences of any length L >= 3 (all L
+ * symbols free, a flip negates one symbol, every shift k counts): the unrestricted problem the
+ * skew-symmetric restriction of Section 1 reduces.
  * ---------------------------------------------------------------------------------------- */
 
 typedef struct {
@@ -312,7 +354,8 @@ typedef struct {
     uint64_t seed;
     uint32_t walk_id;
     uint32_t flags;         /* ORACLE_BRUTE: score flips by the plain definition;
-                               ORACLE_IDEAL: exact visited set instead of the bounded table */
+                               ORACLE_IDEAL: exact visited set instead of the bounded table;
+                               ORACLE_GENERAL: general sequences (ref_walk only) */
     int64_t steps;          /* iteration budget */
     int64_t restart_period; /* 0 = never */
     int64_t target_isl;     /* -1 = none; else stop after the first state with ISL <= target */
@@ -328,6 +371,7 @@ typedef struct {
 
 #define ORACLE_BRUTE 1u
 #define ORACLE_IDEAL 2u
+#define ORACLE_GENERAL 4u
 
 /* Exact visited set used with ORACLE_IDEAL: open addressing over whole free-bit vectors. */
 typedef struct {
@@ -441,9 +485,12 @@ static void to_u32_words(const uint64_t *x, int32_t nwords, uint32_t *out)
 int ref_walk(const ref_walk_cfg *cfg, ref_walk_result *res, int32_t *trace, int32_t *score_trace)
 {
     const int32_t L = cfg->L;
-    if (L < 3 || (L % 2) == 0 || cfg->steps < 0 || cfg->table_log2 < 1 || cfg->table_log2 > 30)
+    const int general = (cfg->flags & ORACLE_GENERAL) != 0;
+    if (L < 3 || (!general && (L % 2) == 0) || cfg->steps < 0 || cfg->table_log2 < 1 || cfg->table_log2 > 30)
         return -1;
-    const int32_t n = (L + 1) / 2, c = n - 1;
+    /* skew: n = c + 1 free symbols (flip j also negates the mirror L-1-j unless j = c);
+     * general: all L symbols are free and a flip negates one */
+    const int32_t n = general ? L : (L + 1) / 2, c = general ? -1 : n - 1;
     const int32_t nwords = (n + 63) / 64;
     if (nwords > ORACLE_MAX_WORDS)
         return -1;
@@ -481,8 +528,14 @@ int ref_walk(const ref_walk_cfg *cfg, ref_walk_result *res, int32_t *trace, int3
  * record and insert the start state (Algorithm 1's initialisation). */
 #define START_STATE()                                                                          \
     do {                                                                                       \
-        ref_start_bits(L, cfg->seed, cfg->walk_id, restart, x, nwords);                        \
-        ref_skew_expand(L, x, s);                                                              \
+        if (general) {                                                                         \
+            ref_start_bits_general(L, cfg->seed, cfg->walk_id, restart, x, nwords);            \
+            for (int32_t i = 0; i < L; i++)                                                    \
+                s[i] = ((x[i / 64] >> (i % 64)) & 1u) ? -1 : 1;                                \
+        } else {                                                                               \
+            ref_start_bits(L, cfg->seed, cfg->walk_id, restart, x, nwords);                    \
+            ref_skew_expand(L, x, s);                                                          \
+        }                                                                                      \
         ref_corr(L, s, C);                                                                     \
         isl = 0;                                                                               \
         for (int32_t k = 1; k < L; k++)                                                        \
@@ -512,8 +565,12 @@ int ref_walk(const ref_walk_cfg *cfg, ref_walk_result *res, int32_t *trace, int3
     int64_t t = 0, flips = 0;
     while (t < cfg->steps && !(cfg->target_isl >= 0 && res->hit_step >= 0)) {
         /* score every flip of the current state */
-        for (int32_t j = 0; j < n; j++)
-            score[j] = brute ? ref_flip_isl_brute(L, s, j) : ref_flip_isl_incr(L, s, C, j);
+        for (int32_t j = 0; j < n; j++) {
+            if (general)
+                score[j] = brute ? ref_flip_isl_general_brute(L, s, j) : ref_flip_isl_general_incr(L, s, C, j);
+            else
+                score[j] = brute ? ref_flip_isl_brute(L, s, j) : ref_flip_isl_incr(L, s, C, j);
+        }
         flips += n;
         if (score_trace)
             for (int32_t j = 0; j < n; j++)
@@ -548,7 +605,7 @@ int ref_walk(const ref_walk_cfg *cfg, ref_walk_result *res, int32_t *trace, int3
 
         /* commit the move */
         s[jb] = (int8_t)(-s[jb]);
-        if (jb != c)
+        if (!general && jb != c)
             s[L - 1 - jb] = (int8_t)(-s[L - 1 - jb]);
         x[jb / 64] ^= (uint64_t)1 << (jb % 64);
         h ^= z[jb];

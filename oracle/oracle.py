@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "liblabs_oracle.so")
 MAX_WORDS = 8  # 64-bit free-bit words, n <= 512
 BRUTE = 1
 IDEAL = 2
+GENERAL = 4
 
 _lib = None
 
@@ -68,6 +69,13 @@ def lib():
     L.ref_pq_walk.argtypes = [ctypes.POINTER(WalkCfg), ctypes.c_int32, ctypes.c_int32,
                               ctypes.POINTER(WalkResult), i32p, i32p]
     L.ref_pq_walk.restype = ctypes.c_int
+    L.ref_flip_isl_general_brute.argtypes = [ctypes.c_int32, i8p, ctypes.c_int32]
+    L.ref_flip_isl_general_brute.restype = ctypes.c_int64
+    L.ref_flip_isl_general_incr.argtypes = [ctypes.c_int32, i8p, i64p, ctypes.c_int32]
+    L.ref_flip_isl_general_incr.restype = ctypes.c_int64
+    L.ref_start_bits_general.argtypes = [
+        ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, u64p, ctypes.c_int32
+    ]
     L.ref_enum_skew.argtypes = [ctypes.c_int32, i64p]
     L.ref_enum_skew.restype = ctypes.c_int
     L.ref_enum_skew_min.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64, i64p, u64p, u64p]
@@ -216,6 +224,24 @@ def start_bits(L: int, seed: int, walk_id: int, restart: int) -> int:
     return sum(int(arr[w]) << (64 * w) for w in range(MAX_WORDS))
 
 
+def start_bits_general(L: int, seed: int, walk_id: int, restart: int) -> int:
+    arr = (ctypes.c_uint64 * MAX_WORDS)()
+    lib().ref_start_bits_general(L, seed & 0xFFFFFFFFFFFFFFFF, walk_id, restart, arr, MAX_WORDS)
+    return sum(int(arr[w]) << (64 * w) for w in range(MAX_WORDS))
+
+
+def flip_isl_general(s, j, C=None):
+    """ISL of the general sequence s with s_j negated: by the plain definition, or incrementally
+    from the correlation table C when it is given."""
+    s = np.ascontiguousarray(s, dtype=np.int8)
+    i8p = ctypes.POINTER(ctypes.c_int8)
+    if C is None:
+        return int(lib().ref_flip_isl_general_brute(len(s), s.ctypes.data_as(i8p), j))
+    C = np.ascontiguousarray(C, dtype=np.int64)
+    return int(lib().ref_flip_isl_general_incr(len(s), s.ctypes.data_as(i8p),
+                                               C.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), j))
+
+
 def zobrist(j: int) -> int:
     return int(lib().ref_zobrist(j))
 
@@ -224,13 +250,14 @@ def zobrist(j: int) -> int:
 
 def walk(L, seed, walk_id=0, steps=1000, table_log2=16, restart_period=0, target_isl=-1,
          watch_isl=-1, brute=False, ideal=False, trace=False, score_trace=False, pq_capacity=0,
-         nbr_table_log2=0):
+         nbr_table_log2=0, general=False):
     """Runs one walk; returns a dict of results (+ 'trace' (steps,2) / 'scores' (steps,n)).
     pq_capacity > 0 runs the best-first search with a queue of that capacity instead (and
-    nbr_table_log2 > 0 adds the second table of evaluated neighbours)."""
-    n = (L + 1) // 2
+    nbr_table_log2 > 0 adds the second table of evaluated neighbours).  general=True walks over
+    general sequences (all L symbols free)."""
+    n = L if general else (L + 1) // 2
     cfg = WalkCfg(L, table_log2, seed & 0xFFFFFFFFFFFFFFFF, walk_id,
-                  (BRUTE if brute else 0) | (IDEAL if ideal else 0),
+                  (BRUTE if brute else 0) | (IDEAL if ideal else 0) | (GENERAL if general else 0),
                   steps, restart_period, target_isl, watch_isl)
     res = WalkResult()
     tr = np.zeros((max(steps, 1), 2), dtype=np.int32) if trace else None
