@@ -11,7 +11,8 @@ unit, Section 3: one evaluated flip = one function evaluation), the roofline of 
 the oracle timed on the host cores on a bounded sample of the same workload, the plain
 one-walk-per-launch form on a sample, and time-to-F >= 8 statistics; then (unless --no-extras)
 an uneven batch of all 52 lengths, the serving workload, the exhaustive skew minimum at L = 61
-and 69, and the best-first search with a bounded queue (with and without the second table).
+and 69, the best-first search with a bounded queue (with and without the second table), and
+the walk over general sequences at L = 192.
 """
 import argparse
 import hashlib
@@ -205,6 +206,23 @@ def best_first(labs, walks=WALKS, steps=1000):
     return out
 
 
+def general_walk(labs, Lg=192, walks=WALKS, steps=2000):
+    """The walk over general sequences (all L symbols free, every shift counts) at the longest
+    supported length: flip evaluations per second and the ALU roofline with 3 (L-1) operations
+    per evaluation (one add and two multiply-adds per shift)."""
+    cfg = [labs.make_cfg(Lg, SEED, w, steps=steps, table_log2=TABLE_LOG2) for w in range(walks)]
+    labs.general_walk_batch(cfg[:256])  # warm the launch path
+    res, ms = labs.general_walk_batch(cfg)
+    evals = sum(r["flip_evals"] for r in res)
+    alg = evals * 3 * (Lg - 1) / (ms / 1000.0) / 1e12
+    best = min(r["best_isl"] for r in res)
+    return {"L": Lg, "walks": walks, "steps_per_walk": steps, "kernel_ms": ms, "flip_evals": evals,
+            "flip_evals_per_s": evals / (ms / 1000.0),
+            "roofline": {"bound": "alu", "achieved": alg, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                         "frac": alg / VALU_PEAK_TOPS, "alg_ops_per_flip": 3 * (Lg - 1)},
+            "best_isl": best, "best_F": Lg * Lg / (2.0 * best)}
+
+
 def enum_alg_ops_per_group(Lx):
     """Word operations to score one sequence with the bit-packed form of Eq. (1)-(2): for each even
     lag k, per 32-bit word of the L - k overlapping positions a funnel shift, a masked xor and a
@@ -255,7 +273,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the serving, uneven-batch, enumeration and best-first measurements")
+                    help="skip the serving, uneven-batch, enumeration, best-first and general-walk measurements")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -343,6 +361,7 @@ def main():
         line["serving"] = serving(labs)
         line["enumeration"] = enumeration(labs)
         line["best_first"] = best_first(labs)
+        line["general_walk"] = general_walk(labs)
     if not args.no_cpu:
         line["cpu_baseline"], _ = cpu_baseline()
     print(json.dumps(line), flush=True)

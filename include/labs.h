@@ -233,6 +233,21 @@ int labs_pq_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, const labs_pq_
                        labs_walk_result *out, int32_t *trace, int32_t *scores, double *kernel_ms,
                        void *stream);
 
+/* ---------------------------------------------------------------------------------------------
+ * The walk over general (not skew-symmetric) sequences: the unrestricted problem that the
+ * skew-symmetric restriction of Section 1 reduces.  Exactly the walk of labs_walk_batch with
+ * n = L free symbols (bit j of x = b_j, drawn as the skew start's words over L bits), a flip
+ * negating one symbol, and every shift k = 1 .. L-1 in Eq. (1)-(2); any 3 <= L <=
+ * LABS_GENERAL_L_MAX, odd or even.  flip_evals counts L per step.
+ * ------------------------------------------------------------------------------------------- */
+#define LABS_GENERAL_L_MAX 192
+
+/* Runs n_walks general walks to completion (one launch per kernel shape; steps <= 2^30 per walk);
+ * arguments and results as labs_pq_walk_batch (scores: steps * L int32 per walk with
+ * LABS_TRACE_SCORES).  Synchronous on stream; allocates and frees its device state. */
+int labs_general_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, labs_walk_result *out,
+                            int32_t *trace, int32_t *scores, double *kernel_ms, void *stream);
+
 typedef struct labs_walk_plan labs_walk_plan;
 
 /* Allocates device state for n_walks walks (visited tables: n_walks * 2^table_log2 * 8 bytes;

@@ -45,7 +45,7 @@ EXPORTS = [
     "labs_flip_scores_dev",
     "labs_walk_batch", "labs_walk_plan_create", "labs_walk_plan_run", "labs_walk_plan_results",
     "labs_walk_plan_get_opts", "labs_walk_plan_last_timing", "labs_walk_plan_destroy",
-    "labs_autotune", "labs_pq_walk_batch",
+    "labs_autotune", "labs_pq_walk_batch", "labs_general_walk_batch",
     "labs_server_create", "labs_search_submit", "labs_search_poll", "labs_search_wait",
     "labs_search_cancel", "labs_server_stats", "labs_server_destroy",
 ]
@@ -198,6 +198,7 @@ def lib():
     L.labs_autotune.argtypes = [i32, i32, P(PlanOpts)]
     L.labs_pq_walk_batch.argtypes = [i32, P(WalkCfg), P(PqOpts), P(WalkResult), vp, vp,
                                      P(ctypes.c_double), vp]
+    L.labs_general_walk_batch.argtypes = [i32, P(WalkCfg), P(WalkResult), vp, vp, P(ctypes.c_double), vp]
     L.labs_server_create.argtypes = [P(ServerOpts), P(vp)]
     L.labs_search_submit.argtypes = [vp, P(SearchReq), P(u64)]
     L.labs_search_poll.argtypes = [vp, u64, P(SearchStatus)]
@@ -329,13 +330,13 @@ def _result_dict(r, n):
     }
 
 
-def _split_traces(cfgs, trace_buf, score_buf):
+def _split_traces(cfgs, trace_buf, score_buf, general=False):
     import numpy as np
 
     traces, scores = [], []
     to = so = 0
     for c in cfgs:
-        n = (c.L + 1) // 2
+        n = c.L if general else (c.L + 1) // 2
         if c.flags & TRACE:
             traces.append(np.frombuffer(trace_buf, dtype=np.int32)[2 * to: 2 * (to + c.steps)].reshape(c.steps, 2).copy())
             to += c.steps
@@ -447,6 +448,30 @@ def pq_walk_batch(cfgs, capacity, nbr_table_log2=0, stream=None):
            "labs_pq_walk_batch")
     out = [_result_dict(res[i], (cfgs[i].L + 1) // 2) for i in range(len(cfgs))]
     traces, scores = _split_traces(cfgs, tbuf.raw if tbuf else b"", sbuf.raw if sbuf else b"")
+    for i in range(len(cfgs)):
+        if traces[i] is not None:
+            out[i]["trace"] = traces[i]
+        if scores[i] is not None:
+            out[i]["scores"] = scores[i]
+    return out, ms.value
+
+
+def general_walk_batch(cfgs, stream=None):
+    """labs_general_walk_batch: walks over general (not skew-symmetric) sequences; returns
+    (result dicts with traces if asked, device milliseconds).  Bits cover all L symbols."""
+    cfgs = list(cfgs)
+    arr = (WalkCfg * len(cfgs))(*cfgs)
+    res = (WalkResult * len(cfgs))()
+    tr = sum(c.steps for c in cfgs if c.flags & TRACE)
+    sc = sum(c.steps * c.L for c in cfgs if c.flags & TRACE_SCORES)
+    tbuf = ctypes.create_string_buffer(8 * tr) if tr else None
+    sbuf = ctypes.create_string_buffer(4 * sc) if sc else None
+    ms = ctypes.c_double()
+    s = _stream() if stream is None else ctypes.c_void_p(stream)
+    _check(lib().labs_general_walk_batch(len(cfgs), arr, res, tbuf, sbuf, ctypes.byref(ms), s),
+           "labs_general_walk_batch")
+    out = [_result_dict(res[i], cfgs[i].L) for i in range(len(cfgs))]
+    traces, scores = _split_traces(cfgs, tbuf.raw if tbuf else b"", sbuf.raw if sbuf else b"", general=True)
     for i in range(len(cfgs)):
         if traces[i] is not None:
             out[i]["trace"] = traces[i]

@@ -604,31 +604,21 @@ extern "C" int labs_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, labs_w
     return rc;
 }
 
-extern "C" int labs_pq_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, const labs_pq_opts *opts,
-                                  labs_walk_result *out, int32_t *trace, int32_t *scores, double *kernel_ms,
-                                  void *stream)
+namespace liblabs {
+
+// The synchronous one-launch-per-shape batches: the best-first search (nlog2, cap) and the
+// general walk (general = true).
+static int batch_sync(bool general, int32_t n_walks, const labs_walk_cfg *cfg, int cap, int nlog2,
+                      labs_walk_result *out, int32_t *trace, int32_t *scores, double *kernel_ms, void *stream)
 {
-    if (n_walks < 1 || !cfg || !opts || !out)
-        return fail(LABS_EINVAL, "labs_pq_walk_batch: n_walks = %d with cfg, opts and out required", n_walks);
-    if (opts->capacity < 1 || opts->capacity > 64)
-        return fail(LABS_EINVAL, "labs_pq_walk_batch: capacity = %d must be in [1, 64]", opts->capacity);
-    if (opts->nbr_table_log2 < 0 || opts->nbr_table_log2 > 30)
-        return fail(LABS_EINVAL, "labs_pq_walk_batch: nbr_table_log2 = %d must be in [0, 30]", opts->nbr_table_log2);
-    for (int32_t i = 0; i < n_walks; i++) {
-        int rc = walk_cfg_check(cfg[i], i);
-        if (rc)
-            return rc;
-        if (cfg[i].steps >= ((int64_t)1 << 31))
-            return fail(LABS_EINVAL, "labs_pq_walk_batch: walk %d: steps must be below 2^31", i);
-    }
     int rc = check_device();
     if (rc)
         return rc;
-    const int nlog2 = opts->nbr_table_log2;
     std::vector<WalkState> st((size_t)n_walks);
     int64_t table_words = 0, trace_records = 0, score_entries = 0;
     for (int32_t i = 0; i < n_walks; i++) {
         const labs_walk_cfg &c = cfg[i];
+        const int n = general ? c.L : (c.L + 1) / 2;
         WalkState &w = st[(size_t)i];
         memset(&w, 0, sizeof w);
         w.L = c.L;
@@ -647,24 +637,25 @@ extern "C" int labs_pq_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, con
             trace_records += c.steps;
         w.score_offset = (c.flags & LABS_TRACE_SCORES) ? score_entries : -1;
         if (c.flags & LABS_TRACE_SCORES)
-            score_entries += c.steps * ((c.L + 1) / 2);
+            score_entries += c.steps * n;
         w.step_cap = INT64_MAX;
         w.hit_step = -1;
         w.watch_step = -1;
         w.status = kFresh;
     }
     // one launch per kernel shape, over the walks of that shape
+    auto shape_of = [&](int L) { return general ? general_shape_for_length(L) : shape_for_length(L); };
     std::vector<int32_t> order((size_t)n_walks);
     std::vector<int32_t> first(9, 0);
     {
         std::vector<int32_t> count(8, 0);
         for (int32_t i = 0; i < n_walks; i++)
-            count[(size_t)shape_for_length(cfg[i].L)]++;
+            count[(size_t)shape_of(cfg[i].L)]++;
         for (int s = 0; s < 8; s++)
             first[(size_t)s + 1] = first[(size_t)s] + count[(size_t)s];
         std::vector<int32_t> fill(first.begin(), first.end() - 1);
         for (int32_t i = 0; i < n_walks; i++)
-            order[(size_t)fill[(size_t)shape_for_length(cfg[i].L)]++] = i;
+            order[(size_t)fill[(size_t)shape_of(cfg[i].L)]++] = i;
     }
     hipStream_t s = (hipStream_t)stream;
     WalkState *d_st = nullptr;
@@ -687,9 +678,13 @@ extern "C" int labs_pq_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, con
     if (e == hipSuccess) e = hipEventRecord(ev0, s);
     for (int sh = 7; e == hipSuccess && sh >= 0; sh--) {
         const int32_t cnt = first[(size_t)sh + 1] - first[(size_t)sh];
-        if (cnt > 0)
-            e = launch_pq_walk(sh, d_st, cnt, d_order + first[(size_t)sh], d_tables, d_nbr, nlog2, opts->capacity,
-                               d_trace, d_scores, s);
+        if (cnt <= 0)
+            continue;
+        if (general)
+            e = launch_walk_general(sh, d_st, cnt, d_order + first[(size_t)sh], d_tables, d_trace, d_scores, s);
+        else
+            e = launch_pq_walk(sh, d_st, cnt, d_order + first[(size_t)sh], d_tables, d_nbr, nlog2, cap, d_trace,
+                               d_scores, s);
     }
     if (e == hipSuccess) e = hipEventRecord(ev1, s);
     if (e == hipSuccess) e = hipMemcpyAsync(st.data(), d_st, sizeof(WalkState) * (size_t)n_walks, hipMemcpyDeviceToHost, s);
@@ -708,7 +703,7 @@ extern "C" int labs_pq_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, con
     if (d_scores) (void)hipFree(d_scores);
     if (d_order) (void)hipFree(d_order);
     if (e != hipSuccess)
-        return hip_fail(e, "labs_pq_walk_batch");
+        return hip_fail(e, general ? "labs_general_walk_batch" : "labs_pq_walk_batch");
     for (int32_t i = 0; i < n_walks; i++) {
         const WalkState &w = st[(size_t)i];
         labs_walk_result &r = out[i];
@@ -730,6 +725,49 @@ extern "C" int labs_pq_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, con
     if (kernel_ms)
         *kernel_ms = (double)ms;
     return LABS_OK;
+}
+
+} // namespace liblabs
+
+extern "C" int labs_pq_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, const labs_pq_opts *opts,
+                                  labs_walk_result *out, int32_t *trace, int32_t *scores, double *kernel_ms,
+                                  void *stream)
+{
+    if (n_walks < 1 || !cfg || !opts || !out)
+        return fail(LABS_EINVAL, "labs_pq_walk_batch: n_walks = %d with cfg, opts and out required", n_walks);
+    if (opts->capacity < 1 || opts->capacity > 64)
+        return fail(LABS_EINVAL, "labs_pq_walk_batch: capacity = %d must be in [1, 64]", opts->capacity);
+    if (opts->nbr_table_log2 < 0 || opts->nbr_table_log2 > 30)
+        return fail(LABS_EINVAL, "labs_pq_walk_batch: nbr_table_log2 = %d must be in [0, 30]", opts->nbr_table_log2);
+    for (int32_t i = 0; i < n_walks; i++) {
+        int rc = walk_cfg_check(cfg[i], i);
+        if (rc)
+            return rc;
+        if (cfg[i].steps >= ((int64_t)1 << 31))
+            return fail(LABS_EINVAL, "labs_pq_walk_batch: walk %d: steps must be below 2^31", i);
+    }
+    return batch_sync(false, n_walks, cfg, opts->capacity, opts->nbr_table_log2, out, trace, scores, kernel_ms,
+                      stream);
+}
+
+extern "C" int labs_general_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, labs_walk_result *out,
+                                       int32_t *trace, int32_t *scores, double *kernel_ms, void *stream)
+{
+    if (n_walks < 1 || !cfg || !out)
+        return fail(LABS_EINVAL, "labs_general_walk_batch: n_walks = %d with cfg and out required", n_walks);
+    for (int32_t i = 0; i < n_walks; i++) {
+        const labs_walk_cfg &c = cfg[i];
+        if (c.L < 3 || c.L > LABS_GENERAL_L_MAX)
+            return fail(LABS_EINVAL, "walk %d: L = %d must be in [3, %d]", i, c.L, LABS_GENERAL_L_MAX);
+        labs_walk_cfg odd = c;
+        odd.L = 3; // the remaining checks do not depend on L
+        int rc = walk_cfg_check(odd, i);
+        if (rc)
+            return rc;
+        if (c.steps > ((int64_t)1 << 30))
+            return fail(LABS_EINVAL, "labs_general_walk_batch: walk %d: steps must be at most 2^30", i);
+    }
+    return batch_sync(true, n_walks, cfg, 0, 0, out, trace, scores, kernel_ms, stream);
 }
 
 // =============================================================================================

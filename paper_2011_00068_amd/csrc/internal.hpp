@@ -78,6 +78,9 @@ hipError_t launch_flip_scores(int32_t variant, int L, int count, const uint32_t 
 hipError_t launch_isl_batch(int L, int count, const int8_t *s, int64_t *isl, double *F,
                             int32_t *psl, int32_t *corr, hipStream_t stream);
 hipError_t launch_enum_skew(int L, int32_t *isl, hipStream_t stream);
+int general_shape_for_length(int L);
+hipError_t launch_walk_general(int shape, WalkState *states, int32_t count, const int32_t *order, uint64_t *tables,
+                               int32_t *trace, int32_t *scores, hipStream_t stream);
 hipError_t launch_pq_walk(int shape, WalkState *states, int32_t count, const int32_t *order, uint64_t *tables,
                           uint64_t *nbr_tables, int nlog2, int cap, int32_t *trace, int32_t *scores,
                           hipStream_t stream);

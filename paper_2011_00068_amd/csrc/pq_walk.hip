@@ -127,12 +127,10 @@ __device__ __forceinline__ void run_pq(WalkState *__restrict__ wsp, uint64_t *__
 
     W w;
     w.lane = lane;
-    w.L = su(ws.L);
-    w.c = (w.L - 1) / 2;
-    w.n = w.c + 1;
+    w.set_length(su(ws.L));
     w.lds = lds;
     w.zk = zk;
-    w.setup_lanes(lane);
+    w.init_lanes(lane);
     const int n = w.n;
     const int tlog2 = su(ws.table_log2);
     const bool exact = n <= tlog2;

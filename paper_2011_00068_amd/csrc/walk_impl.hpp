@@ -118,6 +118,7 @@ struct FlipConst {
 // ---------------------------------------------------------------------------------------------
 template <int G, int KW, bool DIRECT>
 struct Walker {
+    static constexpr int kG = G;
     static constexpr int QR = (KW + 1) / 2; // lane-held C registers: kappa = lane + 64 q
     using Lds = typename LdsOf<DIRECT>::type;
 
@@ -132,6 +133,19 @@ struct Walker {
     Lds *lds;
     const uint64_t *zk;
     FlipConst fc[G];
+
+    __device__ __forceinline__ void set_length(int len)
+    {
+        L = len;
+        c = (L - 1) / 2;
+        n = c + 1;
+    }
+
+    __device__ __forceinline__ void init_lanes(int ln)
+    {
+        if constexpr (!DIRECT)
+            setup_lanes(ln);
+    }
 
     // Per-lane constants of the owned flips (bit-sliced variant).
     __device__ __forceinline__ void setup_lanes(int ln)
@@ -484,12 +498,12 @@ __device__ inline uint64_t slot_of(uint64_t hh, uint32_t x0, bool exact, int log
 // ---------------------------------------------------------------------------------------------
 // One walk, advanced until its budget, its target, or the launch's step limit.
 // ---------------------------------------------------------------------------------------------
-template <int G, int KW, bool DIRECT, int PW>
+template <class W, int PW>
 __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *__restrict__ tables,
                          int32_t *__restrict__ trace, int32_t *__restrict__ scores, int64_t chunk,
-                         typename LdsOf<DIRECT>::type *lds, const uint64_t *zk)
+                         typename W::Lds *lds, const uint64_t *zk)
 {
-    using W = Walker<G, KW, DIRECT>;
+    constexpr int G = W::kG;
     int lane = lane_id();
     asm volatile("" : "+v"(lane)); // nothing lane-derived is hoisted out of the walk
     WalkState &ws = *wsp;
@@ -500,13 +514,10 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
 
     W w;
     w.lane = lane;
-    w.L = su(ws.L);
-    w.c = (w.L - 1) / 2;
-    w.n = w.c + 1;
+    w.set_length(su(ws.L));
     w.lds = lds;
     w.zk = zk;
-    if constexpr (!DIRECT)
-        w.setup_lanes(lane);
+    w.init_lanes(lane);
     const int L = w.L, n = w.n;
     const int tlog2 = su(ws.table_log2);
     const bool exact = n <= tlog2;
@@ -813,17 +824,17 @@ __device__ __forceinline__ void run_any(WalkState *ws, uint64_t *tables, int32_t
                                int64_t chunk, typename LdsOf<DIRECT>::type *lds, const uint64_t *zk)
 {
     if constexpr (SHAPE >= 0) {
-        run_walk<ShapeGK<SHAPE>::G, ShapeGK<SHAPE>::KW, DIRECT, PW>(ws, tables, trace, scores, chunk, lds, zk);
+        run_walk<Walker<ShapeGK<SHAPE>::G, ShapeGK<SHAPE>::KW, DIRECT>, PW>(ws, tables, trace, scores, chunk, lds, zk);
     } else {
         switch (shape_for_length_dev(ws->L)) {
-        case 0: run_walk<1, 1, DIRECT, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
-        case 1: run_walk<1, 2, DIRECT, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
-        case 2: run_walk<2, 2, DIRECT, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
-        case 3: run_walk<2, 3, DIRECT, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
-        case 4: run_walk<2, 4, DIRECT, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
-        case 5: run_walk<3, 4, DIRECT, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
-        case 6: run_walk<3, 5, DIRECT, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
-        default: run_walk<3, 6, DIRECT, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
+        case 0: run_walk<Walker<1, 1, DIRECT>, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
+        case 1: run_walk<Walker<1, 2, DIRECT>, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
+        case 2: run_walk<Walker<2, 2, DIRECT>, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
+        case 3: run_walk<Walker<2, 3, DIRECT>, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
+        case 4: run_walk<Walker<2, 4, DIRECT>, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
+        case 5: run_walk<Walker<3, 4, DIRECT>, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
+        case 6: run_walk<Walker<3, 5, DIRECT>, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
+        default: run_walk<Walker<3, 6, DIRECT>, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
         }
     }
 }
