@@ -16,7 +16,9 @@
 //   G_j = sum_k C_k u_jk,  H_j = sum_k u_jk^2.
 // Two variants compute it:
 //  * BITSLICE: C is held as P two's-complement bit planes (P = bits of max |C_k|, one ballot
-//    per plane) and the sequence as bit strings split by index parity; the windows
+//    per plane; the two lowest planes are constant, since every even-shift correlation of a
+//    skew sequence is congruent to L mod 4) and the sequence as bit strings split by index
+//    parity; the windows
 //    Wp[kappa] = b_{j+k}, Wq[kappa] = b_{j-k} are funnel shifts of those strings, so
 //      sum_kappa C_kappa (Wp + Wq) = sum_t w_t [popc(plane_t & Wp) + popc(plane_t & Wq)],
 //    and with prefix sums of C (PSX) over the valid shifts
@@ -338,7 +340,9 @@ struct Walker {
                     acc[g] = -(int32_t)s;
                 }
             }
-            for (int t = planes - 2; t >= 0; t--) {
+            // planes 2 .. P-2 from ballots; at least three planes, so that the sign plane is never
+            // one of the two lowest
+            for (int t = max(planes, 3) - 2; t >= 2; t--) {
                 uint32_t pl[KW];
 #pragma unroll
                 for (int q = 0; q < QR; q++) {
@@ -357,6 +361,24 @@ struct Walker {
                     for (int w = 0; w <= g; w++)
                         s = bcnt_acc(pl[w] & wq[g][w], s);
                     acc[g] = (int32_t)s;
+                }
+            }
+            // the two lowest planes are the same for every shift: a flip moves C_k by a multiple of
+            // 4 and the flips connect every skew sequence of length L, so all even-shift
+            // correlations are congruent mod 4 (to L), odd: bit 0 is set, bit 1 is set iff
+            // L = 3 mod 4.  Their contribution is r * popcount(W) with r = L mod 4.
+            {
+                const int32_t r = L & 3;
+#pragma unroll
+                for (int g = 0; g < G; g++) {
+                    uint32_t sw = 0;
+#pragma unroll
+                    for (int w = 0; w < KW - g; w++)
+                        sw = bcnt_acc(wp[g][w], sw);
+#pragma unroll
+                    for (int w = 0; w <= g; w++)
+                        sw = bcnt_acc(wq[g][w], sw);
+                    acc[g] = (acc[g] << 2) + r * (int32_t)sw;
                 }
             }
             // assemble ISL_j (products with +-1 are conditional negations).  For the centre, Wp

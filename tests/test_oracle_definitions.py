@@ -217,3 +217,15 @@ def test_start_bits_are_masked_and_distinct():
         assert len(xs) == min(64, 1 << n)
         assert all(x < (1 << n) for x in xs)
         assert o.start_bits(L, 5, 1, 0) != o.start_bits(L, 5, 1, 1)
+
+
+def test_even_shift_correlations_are_congruent_to_L_mod_4():
+    # every flip moves an even-shift correlation by a multiple of 4 (the incremental formula) and
+    # flips connect all skew sequences, so C_k mod 4 is the same for every skew sequence of one
+    # length: it equals L mod 4 (the bit-sliced scoring relies on it)
+    rng = random.Random(13)
+    for L in list(range(3, 80, 2)) + [101, 127, 201, 255, 257, 303, 383]:
+        n = (L + 1) // 2
+        for _ in range(4):
+            C = o.corr(o.skew_expand(L, rng.getrandbits(n)))
+            assert all(int(C[k]) % 4 == L % 4 for k in range(2, L, 2)), L
