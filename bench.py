@@ -40,7 +40,8 @@ WATCH_ISL = (L * L * 1) // (2 * 8)  # F >= 8    <=>  ISL <= floor(L^2 / 16) = 40
 ALG_OPS_PER_FLIP = 3 * (L - 1) // 2
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz int32 VALU lane-operations per second
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-KERNEL_SOURCES = ["paper_2011_00068_amd/csrc/walk_impl.hpp", "paper_2011_00068_amd/csrc/device_common.hpp"]
+KERNEL_SOURCES = ["paper_2011_00068_amd/csrc/walk_impl.hpp", "paper_2011_00068_amd/csrc/device_common.hpp",
+                  "paper_2011_00068_amd/csrc/mfma_walker.hpp", "paper_2011_00068_amd/csrc/walk_inst_mfma.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_L255_16384_traffic.json")
 
 
@@ -272,6 +273,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--variant", type=int, default=0,
+                    help="walk kernel variant: 0 auto, 1 bit-sliced, 2 direct, 3 matrix cores")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
     ap.add_argument("--no-extras", action="store_true",
@@ -301,7 +304,7 @@ def main():
     import paper_2011_00068_amd as labs
 
     torch.cuda.set_device(0)
-    plan = labs.WalkPlan(cfgs(labs, WALKS, STEPS))
+    plan = labs.WalkPlan(cfgs(labs, WALKS, STEPS), variant=args.variant)
     opts = plan.opts()
     for _ in range(args.warmup):
         plan.run()
@@ -330,7 +333,8 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                 "frac": achieved / VALU_PEAK_TOPS,
                 "traffic": cnt["hbm_bytes_per_launch"] if cnt else None,
-                "kernel": "k_walk", "kernel_ms_per_launch": per_launch_ms,
+                "kernel": "k_walk_mfma" if opts["variant"] == 3 else "k_walk",
+                "kernel_ms_per_launch": per_launch_ms,
                 "alg_ops_per_flip": ALG_OPS_PER_FLIP,
                 # rocprofv3 counters of the same launch: share of VALU issue cycles in use, and
                 # VALU instructions per walk step (128 flip evaluations)

@@ -35,6 +35,7 @@ TRACE_SCORES = 2
 VARIANT_AUTO = 0
 VARIANT_BITSLICE = 1
 VARIANT_DIRECT = 2
+VARIANT_MFMA = 3
 
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_CANCELLED = 0, 1, 2, 3
 

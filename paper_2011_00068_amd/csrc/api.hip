@@ -271,8 +271,10 @@ extern "C" int labs_flip_scores_dev(int32_t L, int32_t count, const uint32_t *x_
         return fail(LABS_EINVAL, "labs_flip_scores_dev: bad arguments (L = %d, count = %d)", L, count);
     if (variant == LABS_VARIANT_AUTO)
         variant = LABS_VARIANT_BITSLICE;
-    if (variant != LABS_VARIANT_BITSLICE && variant != LABS_VARIANT_DIRECT)
+    if (variant != LABS_VARIANT_BITSLICE && variant != LABS_VARIANT_DIRECT && variant != LABS_VARIANT_MFMA)
         return fail(LABS_EINVAL, "labs_flip_scores_dev: unknown variant %d", variant);
+    if (variant == LABS_VARIANT_MFMA && L > kMfmaLMax)
+        return fail(LABS_EINVAL, "labs_flip_scores_dev: the matrix-core variant needs L <= %d", kMfmaLMax);
     int rc = check_device();
     if (rc)
         return rc;
@@ -844,18 +846,24 @@ static int resolve_opts(labs_walk_plan *p, const labs_plan_opts *in)
     int32_t persistent = 0;
     // shapes present
     int shape = -2;
-    int maxL = 0;
+    int maxL = 0, minL = 1 << 30;
     for (const labs_walk_cfg &c : p->cfg) {
         const int s = shape_for_length(c.L);
         shape = (shape == -2 || shape == s) ? s : -1;
         maxL = std::max(maxL, c.L);
+        minL = std::min(minL, c.L);
     }
     labs_plan_opts tuned{};
     const bool have = cache_lookup(maxL, &tuned);
+    // untuned default: the matrix-core scoring where it was measured faster (191 <= L <= 255),
+    // the bit-sliced one elsewhere
     if (o.variant == LABS_VARIANT_AUTO)
-        o.variant = have ? tuned.variant : LABS_VARIANT_BITSLICE;
-    if (o.variant != LABS_VARIANT_BITSLICE && o.variant != LABS_VARIANT_DIRECT)
+        o.variant = have ? tuned.variant
+                         : ((minL >= kMfmaAutoLMin && maxL <= kMfmaLMax) ? LABS_VARIANT_MFMA : LABS_VARIANT_BITSLICE);
+    if (o.variant != LABS_VARIANT_BITSLICE && o.variant != LABS_VARIANT_DIRECT && o.variant != LABS_VARIANT_MFMA)
         return fail(LABS_EINVAL, "unknown variant %d", o.variant);
+    if (o.variant == LABS_VARIANT_MFMA && maxL > kMfmaLMax)
+        return fail(LABS_EINVAL, "the matrix-core variant needs L <= %d (longest walk: %d)", kMfmaLMax, maxL);
     if (o.waves_per_block == 0)
         o.waves_per_block = have ? tuned.waves_per_block : 1;
     if (o.waves_per_block != 1 && o.waves_per_block != 2 && o.waves_per_block != 4 && o.waves_per_block != 8)
@@ -920,10 +928,12 @@ extern "C" int labs_autotune(int32_t L, int32_t n_walks, labs_plan_opts *best)
     }
     struct Cand { labs_plan_opts o; };
     std::vector<Cand> cands;
-    for (int v : {LABS_VARIANT_BITSLICE, LABS_VARIANT_DIRECT})
+    for (int v : {LABS_VARIANT_BITSLICE, LABS_VARIANT_DIRECT, LABS_VARIANT_MFMA})
         for (int wpb : {1, 2, 4})
             for (int pw : {1, 2})
                 for (int pers : {1, 2}) {
+                    if (v == LABS_VARIANT_MFMA && L > kMfmaLMax)
+                        continue;
                     Cand c{};
                     c.o.variant = v;
                     c.o.waves_per_block = wpb;

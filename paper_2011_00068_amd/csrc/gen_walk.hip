@@ -61,6 +61,8 @@ struct GenWalker {
         c = -1; // no centre: every flip negates one symbol
     }
 
+    __device__ __forceinline__ int flip(int g) const { return lane + 64 * g; }
+
     __device__ __forceinline__ void init_lanes(int) {}
 
     __device__ inline uint32_t bit(int i) const

@@ -143,6 +143,9 @@ struct Walker {
         n = c + 1;
     }
 
+    // flip scored in slot g of this lane
+    __device__ __forceinline__ int flip(int g) const { return lane + 64 * g; }
+
     __device__ __forceinline__ void init_lanes(int ln)
     {
         if constexpr (!DIRECT)
@@ -651,7 +654,7 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
             uint32_t keys[G];
 #pragma unroll
             for (int g = 0; g < G; g++) {
-                const int j = w.lane + 64 * g;
+                const int j = w.flip(g);
                 keys[g] = (j < n) ? (((uint32_t)isl_j[g] << 8) | (uint32_t)j) : 0xFFFFFFFFu;
                 if (scp && j < n)
                     scp[j] = isl_j[g];
@@ -672,7 +675,7 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
                     if (cand[i] != 0xFFFFFFFFu) {
 #pragma unroll
                         for (int g = 0; g < G; g++)
-                            keys[g] = (w.lane + 64 * g == (int)(cand[i] & 255u)) ? 0xFFFFFFFFu : keys[g];
+                            keys[g] = (w.flip(g) == (int)(cand[i] & 255u)) ? 0xFFFFFFFFu : keys[g];
                     }
                 }
                 if (cand[0] == 0xFFFFFFFFu)
@@ -951,5 +954,6 @@ WalkKernel pick_walk_kernel_bits_pw1(int shape);
 WalkKernel pick_walk_kernel_bits_pw2(int shape);
 WalkKernel pick_walk_kernel_direct_pw1(int shape);
 WalkKernel pick_walk_kernel_direct_pw2(int shape);
+WalkKernel pick_walk_kernel_mfma(int shape); // nullptr for shapes with c > 127
 
 } // namespace liblabs

@@ -31,6 +31,8 @@ __global__ void k_reset(WalkState *__restrict__ states, const WalkState *__restr
 
 static WalkKernel pick_kernel(const WalkLaunch &lp)
 {
+    if (lp.variant == LABS_VARIANT_MFMA)
+        return pick_walk_kernel_mfma(lp.shape);
     const bool direct = lp.variant == LABS_VARIANT_DIRECT;
     return direct ? (lp.probe_width >= 2 ? pick_walk_kernel_direct_pw2(lp.shape)
                                          : pick_walk_kernel_direct_pw1(lp.shape))
@@ -38,12 +40,20 @@ static WalkKernel pick_kernel(const WalkLaunch &lp)
                                          : pick_walk_kernel_bits_pw1(lp.shape));
 }
 
+static size_t wave_lds_bytes(int variant)
+{
+    if (variant == LABS_VARIANT_MFMA)
+        return mfma_wave_lds_bytes();
+    return variant == LABS_VARIANT_DIRECT ? sizeof(WaveLdsDirect) : sizeof(WaveLdsBits);
+}
+
 int resident_walk_waves(const WalkLaunch &lp)
 {
-    const bool direct = lp.variant == LABS_VARIANT_DIRECT;
     const int wpb = lp.waves_per_block;
-    const size_t lds = (size_t)wpb * (direct ? sizeof(WaveLdsDirect) : sizeof(WaveLdsBits));
+    const size_t lds = (size_t)wpb * wave_lds_bytes(lp.variant);
     int blocks = 0, dev = 0, cus = 0;
+    if (!pick_kernel(lp))
+        return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void *>(pick_kernel(lp)),
                                                      64 * wpb, lds) != hipSuccess)
         return 0;
@@ -56,12 +66,13 @@ hipError_t launch_walk(const WalkLaunch &lp, WalkState *states, int32_t n_walks,
                        uint64_t *tables, int32_t *trace, int32_t *scores, int32_t *counter,
                        hipStream_t stream)
 {
-    const bool direct = lp.variant == LABS_VARIANT_DIRECT;
     WalkKernel k = pick_kernel(lp);
     const int wpb = lp.waves_per_block;
+    if (!k)
+        return hipErrorInvalidValue;
     if (wpb < 1 || wpb > kMaxWavesPerBlock)
         return hipErrorInvalidConfiguration; // the kernel is compiled for at most 8 waves per block
-    const size_t lds = (size_t)wpb * (direct ? sizeof(WaveLdsDirect) : sizeof(WaveLdsBits));
+    const size_t lds = (size_t)wpb * wave_lds_bytes(lp.variant);
     int blocks;
     int32_t *ctr = nullptr;
     if (lp.persistent) {
@@ -103,6 +114,8 @@ hipError_t launch_flip_scores(int32_t variant, int L, int count, const uint32_t 
 {
     if (count <= 0)
         return hipSuccess;
+    if (variant == LABS_VARIANT_MFMA)
+        return launch_flip_scores_mfma(L, count, x, scores, stream);
     const bool direct = variant == LABS_VARIANT_DIRECT;
     void (*k)(int, int, const uint32_t *, int32_t *) = nullptr;
 #define LABS_PICK(S)                                                                                  \

@@ -40,7 +40,7 @@ def assert_same(g, r, what=""):
         assert np.array_equal(g["scores"][:T], r["scores"][:T]), what
 
 
-@pytest.mark.parametrize("variant", [1, 2], ids=["bitslice", "direct"])
+@pytest.mark.parametrize("variant", [1, 2, 3], ids=["bitslice", "direct", "mfma"])
 def test_l31_single_walk_full_trajectory(labs, variant):
     # L = 31, one walk of 20,000 steps, exact table (2^16 >= 2^n): every step's chosen flip, ISL
     # and all 16 flip scores equal the oracle's.
@@ -60,7 +60,7 @@ def test_short_walks_every_shape(labs, L):
     # every kernel shape (flip groups x window words), edge lengths included
     cfgs = [labs.make_cfg(L, SEED + L, w, steps=300, table_log2=12, trace=True, score_trace=True)
             for w in range(3)]
-    for variant in (1, 2):
+    for variant in ((1, 2, 3) if L <= 255 else (1, 2)):
         got = labs.WalkPlan(cfgs, variant=variant)
         got.run()
         res = got.results()
@@ -107,7 +107,7 @@ def test_restarts_traps_targets(labs):
         labs.make_cfg(101, SEED, 9, steps=0),
         labs.make_cfg(255, SEED, 3, steps=300, restart_period=64, table_log2=10, trace=True),
     ]
-    for variant in (1, 2):
+    for variant in (1, 2, 3):
         plan = labs.WalkPlan(cfgs, variant=variant)
         plan.run()
         res = plan.results()
@@ -154,6 +154,28 @@ def test_launch_options_do_not_change_results(labs):
         plan.close()
     for i in (0, 5, 10, 15):
         assert_same(ref[i], oracle_walk(cfgs[i], trace=True), i)
+
+
+def test_mfma_launch_options_and_mixed_lengths(labs):
+    # the matrix-core form under every launch option, on a batch mixing its shapes (L <= 255)
+    cfgs = [labs.make_cfg(L, SEED, w, steps=600, table_log2=14, restart_period=200, trace=True)
+            for L in (5, 33, 61, 129, 131, 191, 253, 255) for w in range(3)]
+    ref = None
+    for opt in (dict(variant=1), dict(variant=3), dict(variant=3, waves_per_block=4, persistent=2),
+                dict(variant=3, steps_per_launch=77), dict(variant=3, use_graph=True, steps_per_launch=150)):
+        plan = labs.WalkPlan(cfgs, **opt)
+        plan.run()
+        res = plan.results()
+        plan.close()
+        if ref is None:
+            ref = res
+        for a, b in zip(ref, res):
+            assert_same(a, b, opt)
+    for i in (0, 4, 9, 13, 20, 23):
+        assert_same(ref[i], oracle_walk(cfgs[i], trace=True), i)
+    with pytest.raises(labs.LabsError) as e:
+        labs.WalkPlan([labs.make_cfg(257, SEED, 0, steps=10)], variant=3)
+    assert e.value.code == labs.LABS_EINVAL
 
 
 def test_l255_headline_full_size(labs):
