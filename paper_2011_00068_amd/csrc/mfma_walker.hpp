@@ -197,12 +197,12 @@ struct MfmaWalker {
         lds_fence();
     }
 
-    // C to LDS, prefix sums, magnitude bits; C' bytes for the B operand.
+    // C to LDS, prefix sums, whether C' fits int8; C' bytes for the B operand.
     __device__ __forceinline__ void prepare()
     {
         const int lane = this->lane;
         int32_t running = 0;
-        uint32_t mag = 0;
+        bool wide = false; // some |C_k| above the int8 range
 #pragma unroll
         for (int q = 0; q < QR; q++) {
             const int kappa = lane + 64 * q;
@@ -210,12 +210,11 @@ struct MfmaWalker {
             const int32_t inc = wave_inclusive_scan(Cv[q]) + running;
             lds->psx[kappa + 1] = inc;
             running = readlane_i(inc, 63);
-            mag |= (uint32_t)(Cv[q] ^ (Cv[q] >> 31));
+            wide = wide || (uint32_t)(Cv[q] + 128) > 255u;
         }
         if (lane == 0)
             lds->psx[0] = 0;
-        mag = wave_or_u32(mag);
-        planes = (mag == 0) ? 1 : 33 - __builtin_clz(mag);
+        planes = ballot(wide) != 0ull ? 9 : 8; // only "fits int8 or not" is used
         int8_t *c0 = reinterpret_cast<int8_t *>(lds->cb[0]);
         int8_t *c1 = reinterpret_cast<int8_t *>(lds->cb[1]);
         if (planes <= 8) {
