@@ -29,7 +29,8 @@ namespace liblabs {
 
 namespace {
 
-constexpr int kPqProbe = 4; // visited-table probes issued together
+constexpr int kPqProbe = 4;     // visited-table probes issued together
+constexpr int kPqNearFlips = 6; // an older queue entry this close is reached by single flips
 
 __device__ __forceinline__ bool readlane_b(bool v, int l)
 {
@@ -407,10 +408,33 @@ __device__ __forceinline__ void run_pq(WalkState *__restrict__ wsp, uint64_t *__
                 w.commit(e_j, e_isl);
                 move = e_j;
             } else {
+                // an older entry: reach it by single flips when it is near (each flip updates the
+                // table incrementally), else rebuild from its free bits
+                int dist = 0;
 #pragma unroll
                 for (int i = 0; i < kXWords; i++)
-                    w.x[i] = e_x[i];
-                w.rebuild();
+                    dist += __builtin_popcount(w.x[i] ^ e_x[i]);
+                if (dist <= kPqNearFlips) {
+#pragma unroll
+                    for (int i = 0; i < kXWords; i++) {
+                        uint32_t d = w.x[i] ^ e_x[i];
+                        while (d != 0u) {
+                            const int b = __builtin_ctz(d);
+                            d &= d - 1u;
+                            w.commit(32 * i + b, 0);
+                        }
+                    }
+                    int32_t sq = 0;
+#pragma unroll
+                    for (int q = 0; q < W::QR; q++)
+                        sq += w.Cv[q] * w.Cv[q];
+                    w.isl = wave_sum_i32(sq);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < kXWords; i++)
+                        w.x[i] = e_x[i];
+                    w.rebuild();
+                }
                 move = -2;
             }
             if (w.lane == 0)
