@@ -31,10 +31,12 @@ namespace liblabs {
 typedef int mfma_v4i __attribute__((ext_vector_type(4)));
 
 constexpr int kMfmaSeqDwords = 64; // 256 bytes per string copy
+constexpr int kMfmaSeqStride = 66; // copies 2 dwords apart in bank order: the four copies read by one
+                                   // A load fall on two bank sets instead of one
 constexpr int kMfmaCDwords = 56;   // C' bytes at 16 + kappa, zero elsewhere (reads reach byte 207)
 
 struct WaveLdsMfma : WaveLdsBits {
-    uint32_t sb[4][kMfmaSeqDwords]; // byte copies of the A strings
+    uint32_t sb[4][kMfmaSeqStride]; // byte copies of the A strings (first kMfmaSeqDwords used)
     uint32_t cb[2][kMfmaCDwords];   // C' (or lo) and hi as int8
 };
 
