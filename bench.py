@@ -339,7 +339,9 @@ def main():
                 # rocprofv3 counters of the same launch: share of VALU issue cycles in use, and
                 # VALU instructions per walk step (128 flip evaluations)
                 "counter_valu_issue_frac": cnt["valu_issue_busy_frac"] if cnt else None,
-                "counter_valu_insts_per_step": cnt["valu_insts_per_step"] if cnt else None}
+                "counter_valu_insts_per_step": cnt["valu_insts_per_step"] if cnt else None,
+                "counter_salu_issue_frac": cnt.get("salu_issue_busy_frac") if cnt else None,
+                "counter_mfma_insts_per_step": cnt.get("mfma_insts_per_step") if cnt else None}
 
     line = {
         "metric": "flip-evals/s at L=255 (batched walks, % INT32 VALU peak); p50 time-to-F>=8",
