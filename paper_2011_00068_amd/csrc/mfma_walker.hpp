@@ -12,8 +12,9 @@
 //                                 column nn yields Z at h' = 63 - h),
 //   B[t][nn] = C'_{t-1-nn}        (0 outside 0 <= t-1-nn < c),
 // so D[m][nn] = sum_t A B is Y (kind p) at h and Z (kind 2+p) at 63 - h.  Every A row is an
-// aligned 16-byte window of a byte copy of one string (no shifted copies needed), every B column
-// an unaligned window of one byte array of C' (dword reads plus v_alignbyte).  K = 64 KB covers
+// aligned 16-byte window of a byte copy of one string (no shifted copies needed); every B column
+// is a 16-byte window of C' starting at byte t0 - 1 - nn, read from whichever of four copies of C'
+// shifted by 0..3 bytes puts it on a dword boundary (each step writes C' into all four).  K = 64 KB covers
 // t <= c + 15.  C' fits int8 unless |C_k| > 127; then C' = 64 hi + lo (lo in 0..63, hi in
 // -4..3) and a second pass adds 64 x the hi tile.  Lane layout of the instruction (checked on
 // gfx950): lane l holds row / column l % 16 of A / B and K slice 16 (l / 16) .. +15 in its four
@@ -33,11 +34,12 @@ typedef int mfma_v4i __attribute__((ext_vector_type(4)));
 constexpr int kMfmaSeqDwords = 64; // 256 bytes per string copy
 constexpr int kMfmaSeqStride = 66; // copies 2 dwords apart in bank order: the four copies read by one
                                    // A load fall on two bank sets instead of one
-constexpr int kMfmaCDwords = 56;   // C' bytes at 16 + kappa, zero elsewhere (reads reach byte 207)
+constexpr int kMfmaCDwords = 56;   // one copy of C': byte 20 + kappa - r in copy r, zero elsewhere
+constexpr int kMfmaCBytes = 4 * kMfmaCDwords;
 
 struct WaveLdsMfma : WaveLdsBits {
     uint32_t sb[4][kMfmaSeqStride]; // byte copies of the A strings (first kMfmaSeqDwords used)
-    uint32_t cb[2][kMfmaCDwords];   // C' (or lo) and hi as int8
+    uint32_t cb[4][kMfmaCDwords];   // C' as int8, four copies shifted by 0..3 bytes
 };
 
 __device__ __forceinline__ uint32_t nibble_bytes(uint32_t nib)
@@ -143,10 +145,8 @@ struct MfmaWalker {
             lds->par[lane & 1][6 + (lane >> 1)] = 0u;
         if (lane < 2 * (kRevWords - 6))
             lds->rev[lane & 1][6 + (lane >> 1)] = 0u;
-        if (lane < kMfmaCDwords) {
-            lds->cb[0][lane] = 0u;
-            lds->cb[1][lane] = 0u;
-        }
+        for (int i = lane; i < 4 * kMfmaCDwords; i += kWave)
+            lds->cb[i / kMfmaCDwords][i % kMfmaCDwords] = 0u;
         lds_fence();
         // byte copies of the strings: kind p from par[p] at bit u, kind 2+p from rev[p] at bit
         // 128 + u (= b^p_{63-u}, zero past u = 63)
@@ -217,40 +217,41 @@ struct MfmaWalker {
         if (lane == 0)
             lds->psx[0] = 0;
         planes = ballot(wide) != 0ull ? 9 : 8; // only "fits int8 or not" is used
-        int8_t *c0 = reinterpret_cast<int8_t *>(lds->cb[0]);
-        int8_t *c1 = reinterpret_cast<int8_t *>(lds->cb[1]);
-        if (planes <= 8) {
-#pragma unroll
-            for (int q = 0; q < QR; q++)
-                c0[16 + lane + 64 * q] = (int8_t)Cv[q];
-        } else {
-#pragma unroll
-            for (int q = 0; q < QR; q++) {
-                c0[16 + lane + 64 * q] = (int8_t)(Cv[q] & 63);
-                c1[16 + lane + 64 * q] = (int8_t)(Cv[q] >> 6);
-            }
-        }
+        put_c(planes <= 8 ? 0 : 1); // C' itself, or its low six bits (the high part follows later)
         lds_fence();
     }
 
-    // One K-sweep of the tile with the C' bytes of array `which`.
-    __device__ __forceinline__ mfma_v4i tile(int which) const
+    // C' bytes into the four shifted copies: part 0 C' itself, part 1 its low six bits (0..63),
+    // part 2 C' >> 6 (-4..3 for |C'| <= 253).
+    __device__ __forceinline__ void put_c(int part)
+    {
+        int8_t *cp = reinterpret_cast<int8_t *>(lds->cb[0]) + 20 + lane;
+#pragma unroll
+        for (int q = 0; q < QR; q++) {
+            const int32_t v = part == 0 ? Cv[q] : (part == 1 ? (Cv[q] & 63) : (Cv[q] >> 6));
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+                cp[64 * q + r * (kMfmaCBytes - 1)] = (int8_t)v;
+        }
+    }
+
+    // One K-sweep of the tile with the C' bytes now in the copies.  Lane (slice, nn) needs the
+    // 16 bytes C'_{i0 .. i0+15}, i0 = t0 - 1 - nn; copy r = (i0 + 20) mod 4 holds them from a
+    // dword boundary.
+    __device__ __forceinline__ mfma_v4i tile() const
     {
         const int lane = this->lane;
         const int nn = lane & 15, slice = lane >> 4;
         const int kind = lane & 3, ib = (lane & 15) >> 2;
+        const int r = (3 - nn) & 3;
         mfma_v4i acc = {0, 0, 0, 0};
 #pragma unroll
         for (int kb = 0; kb < KB; kb++) {
             const int t0 = 16 * slice + 64 * kb;
             const uint32_t *ap = &lds->sb[kind][(t0 + 16 * ib) >> 2];
             const mfma_v4i a = {(int)ap[0], (int)ap[1], (int)ap[2], (int)ap[3]};
-            const int s = 16 + t0 - 1 - nn;
-            const uint32_t *bp = &lds->cb[which][s >> 2];
-            const uint32_t sh = (uint32_t)(s & 3);
-            const uint32_t d0 = bp[0], d1 = bp[1], d2 = bp[2], d3 = bp[3], d4 = bp[4];
-            const mfma_v4i b = {(int)alignbyte(d1, d0, sh), (int)alignbyte(d2, d1, sh), (int)alignbyte(d3, d2, sh),
-                                (int)alignbyte(d4, d3, sh)};
+            const uint32_t *bp = &lds->cb[r][(t0 - 1 - nn + 20 - r) >> 2];
+            const mfma_v4i b = {(int)bp[0], (int)bp[1], (int)bp[2], (int)bp[3]};
             acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc, 0, 0, 0);
         }
         return acc;
@@ -259,9 +260,13 @@ struct MfmaWalker {
     __device__ __forceinline__ void score(int32_t (&isl_j)[G])
     {
         const int lane = this->lane;
-        mfma_v4i d = tile(0);
+        mfma_v4i d = tile();
         if (planes > 8) {
-            const mfma_v4i hi = tile(1);
+            // C' = 64 hi + lo: the copies held lo; the wave's LDS operations run in order, so the
+            // reads above complete before the hi bytes overwrite them
+            put_c(2);
+            lds_fence();
+            const mfma_v4i hi = tile();
             d = d + hi * 64;
         }
         // Z for h = lane sits in lane 63 - lane
