@@ -31,8 +31,9 @@ constexpr int kGenWords = 16;          // bit-string words, zero padded past the
 constexpr int kGenRV = kGenLMax - 1;   // reversed string: bit a = b_{kGenRV - a}
 
 struct WaveLdsGen {
-    uint32_t fw[kGenWords];
+    uint32_t fw[kGenWords]; // bit a = b_a: the free bits (words 0 .. kXWords-1), zero padded
     uint32_t rv[kGenWords];
+    uint32_t bestx[kXWords]; // free bits of the best state of the walk so far
     int32_t C[kGenLMax + 1];   // C_k at index k, 0 past L-1
     int32_t psx[kGenLMax + 1]; // psx[a] = sum_{k=1..a} C_k
 };
@@ -47,12 +48,26 @@ struct GenWalker {
     int lane;
     int32_t isl;
     uint64_t h;
-    uint32_t x[kXWords];
+    uint32_t x[kXWords]; // free bits; current only where commit<true> is used (else in lds->fw)
+    uint32_t x0;         // free bits 0..31, always current
     int32_t Cv[QR];
     int32_t sbit[G];
     int planes;
     Lds *lds;
     const uint64_t *zk;
+
+    __device__ __forceinline__ uint32_t *x_lds() const { return lds->fw; }
+    __device__ __forceinline__ uint32_t *best_lds() const { return lds->bestx; }
+
+    // b_js (uniform) from the lane that scores flip js
+    __device__ __forceinline__ uint32_t sbit_of(int js) const
+    {
+        uint32_t v = 0;
+#pragma unroll
+        for (int g = 0; g < G; g++)
+            v = (g == (js >> 6)) ? (uint32_t)__builtin_amdgcn_readlane(sbit[g], js & 63) : v;
+        return v;
+    }
 
     __device__ __forceinline__ void set_length(int len)
     {
@@ -76,6 +91,7 @@ struct GenWalker {
     __device__ __forceinline__ void rebuild()
     {
         const int lane = this->lane;
+        x0 = x[0];
         if (lane < kGenWords) {
             uint32_t f = 0, r = 0;
 #pragma unroll
@@ -230,10 +246,11 @@ struct GenWalker {
     }
 
     // Commit flip js (uniform): C_k += dC_k, bit strings, x, hash.
+    template <bool REG_X = true>
     __device__ __forceinline__ void commit(int js, int32_t isl_new)
     {
         const int lane = this->lane;
-        const int32_t sjs = 1 - 2 * (int32_t)xbit_uniform(x, js);
+        const int32_t sjs = 1 - 2 * (int32_t)(REG_X ? xbit_uniform(x, js) : sbit_of(js));
 #pragma unroll
         for (int q = 0; q < QR; q++) {
             const int k = lane + 64 * q + 1;
@@ -254,7 +271,9 @@ struct GenWalker {
 #pragma unroll
         for (int g = 0; g < G; g++)
             sbit[g] ^= (lane + 64 * g == js) ? 1 : 0;
-        xflip_uniform(x, js);
+        if (REG_X)
+            xflip_uniform(x, js);
+        x0 ^= js < 32 ? 1u << js : 0u;
         const uint64_t z = zk[js];
         h ^= ((uint64_t)uniform((uint32_t)(z >> 32)) << 32) | uniform((uint32_t)z);
         isl = isl_new;

@@ -1,28 +1,39 @@
 // mfma_walker.hpp -- the skew walker with its flip scoring on the matrix cores (gfx950
 // v_mfma_i32_16x16x64_i8), for L <= 255 (c <= 127).
 //
-// The expensive part of scoring is, for every flip j = 2h + p (parity p = j & 1, h = j >> 1),
-//   Y_j = sum_kappa C'_kappa b^p_{h+1+kappa}   and   Z_j = sum_kappa C'_kappa b^p_{h-1-kappa},
-// with C'_kappa = C_{2 kappa + 2} and b^p_u = b_{2u+p} the bits of the parity-p half of the
-// sequence (Y + Z is sum_k C_k (Wp + Wq) of the bit-sliced walker; the assembly of ISL_j from it
-// is the same).  Both are correlations of the small integer vector C' with 0/1 strings, i.e.
-// products of a 0/1 Hankel matrix with a Toeplitz arrangement of C'.  One 16x16 tile holds all
-// of them: row m = 4 i + kind, column nn, h = 16 i + nn, K index t = kappa + 1 + nn:
-//   A[m][t] = S_kind[t + 16 i]   (kind 0/1: b^0, b^1;  kind 2/3: b^p_{63-u}, so that row kind 2+p
-//                                 column nn yields Z at h' = 63 - h),
-//   B[t][nn] = C'_{t-1-nn}        (0 outside 0 <= t-1-nn < c),
-// so D[m][nn] = sum_t A B is Y (kind p) at h and Z (kind 2+p) at 63 - h.  Every A row is an
-// aligned 16-byte window of a byte copy of one string (no shifted copies needed); every B column
-// is a 16-byte window of C' starting at byte t0 - 1 - nn, read from whichever of four copies of C'
-// shifted by 0..3 bytes puts it on a dword boundary (each step writes C' into all four).  K = 64 KB covers
-// t <= c + 15.  C' fits int8 unless |C_k| > 127; then C' = 64 hi + lo (lo in 0..63, hi in
-// -4..3) and a second pass adds 64 x the hi tile.  Lane layout of the instruction (checked on
-// gfx950): lane l holds row / column l % 16 of A / B and K slice 16 (l / 16) .. +15 in its four
-// registers' bytes, and D register r of lane l is D[4 (l / 16) + r][l % 16]; so lane l receives
-// Y_j, Y_{j+1} for h = l and Z for h = 63 - l, which one ds_bpermute brings to lane h.
+// Scoring (derived from Eq. (1) and (4), as in the bit-sliced walker): for flip j = 2h + p
+// (parity p = j & 1, h = j >> 1, mirror m = L-1-j, d = m - j = 2 (c - j), kappa_d = c-1-j)
+//   ISL_j = ISL - 8 s_j G_j + 16 H_j,
+//   G_j = sum_kappa C'_kappa (p_kappa + q_kappa) - C'_{kappa_d} s_m,   C'_kappa = C_{2 kappa + 2},
+//   H_j = np + 3 nq - 1 - 2 [q_d valid] - 4 rc'_j,
+// with p_kappa = s^p_{h+1+kappa}, q_kappa = s^p_{h-1-kappa} (s^p_u = s_{2u+p}, 0 outside the
+// sequence), np / nq the counts of valid p / q shifts and rc'_j the number of both-sided shifts
+// kappa < nq, kappa != kappa_d, where p and q differ.  Since s_m = (-1)^(c-j) s_j, the excluded
+// term contributes 8 (-1)^(c-j) C'_{kappa_d} whatever the sign of s_j, and
+//   ISL_j = ISL + 16 hc_j - 64 rc'_j + 8 (-1)^(c-j) C'_{kappa_d} - 8 s_j T_j,
+//   T_j = Y_j + Z_j,  Y_j = sum_kappa C'_kappa s^p_{h+1+kappa},  Z_j = sum_kappa C'_kappa s^p_{h-1-kappa}.
+// For the centre j = c (p = q, Eq. (4)): G_c = T_c / 2 and H_c = nq, which the same expression
+// gives with hc = nq, no rc' bits, a zero word for C'_{kappa_d} and the factor -4 s_c for T_c.
 //
-// Lane l owns flips j = 2 l and 2 l + 1; the correlation table (lane-held C), its prefix sums,
-// the parity bit strings, the commit and the rest of the assembly are the bit-sliced walker's.
+// Y and Z are correlations of the small integer vector C' with +-1 strings, i.e. products of a
+// Hankel matrix of the sequence with a Toeplitz arrangement of C'.  One 16x16 tile holds all of
+// them: row r = 4 i + kind, column nn, h = 16 i + nn, K index t = kappa + 1 + nn:
+//   A[r][t] = S_kind[t + 16 i]   (kind 0/1: s^0, s^1;  kind 2/3: s^p_{63-u}, so that row kind 2+p
+//                                 column nn yields Z at h' = 63 - h; 0 outside the sequence),
+//   B[t][nn] = C'_{t-1-nn}        (0 outside 0 <= t-1-nn < c),
+// so D[r][nn] = sum_t A B is Y (kind p) at h and Z (kind 2+p) at 63 - h.  Every A row is an
+// aligned 16-byte window of a byte copy of one string; every B column is a 16-byte window of C'
+// starting at byte t0 - 1 - nn, read from whichever of four copies of C' shifted by 0..3 bytes
+// puts it on a dword boundary (each step writes C' into all four).  K = 64 KB covers t <= c + 15.
+// C' fits int8 unless |C_k| > 127; then C' = 64 hi + lo (lo in 0..63, hi in -4..3) and a second
+// pass adds 64 x the hi tile.  Lane layout of the instruction (checked on gfx950): lane l holds
+// row / column l % 16 of A / B and K slice 16 (l / 16) .. +15 in its four registers' bytes, and D
+// register r of lane l is D[4 (l / 16) + r][l % 16]; so lane l receives Y_j, Y_{j+1} for h = l
+// and Z for h = 63 - l, which one ds_bpermute brings to lane h.
+//
+// Lane l owns flips j = 2 l and 2 l + 1 (the same h, both parities), so the two flips share their
+// window offsets.  The correlation table is lane-held as in the bit-sliced walker, and so are the
+// parity bit strings and the commit.
 #pragma once
 
 #include "walk_impl.hpp"
@@ -36,9 +47,15 @@ constexpr int kMfmaSeqStride = 66; // copies 2 dwords apart in bank order: the f
                                    // A load fall on two bank sets instead of one
 constexpr int kMfmaCDwords = 56;   // one copy of C': byte 20 + kappa - r in copy r, zero elsewhere
 constexpr int kMfmaCBytes = 4 * kMfmaCDwords;
+constexpr int kMfmaCWords = 128;   // C' at kappa (0 for kappa >= c; index c serves as the zero word)
 
-struct WaveLdsMfma : WaveLdsBits {
-    uint32_t sb[4][kMfmaSeqStride]; // byte copies of the A strings (first kMfmaSeqDwords used)
+struct WaveLdsMfma {
+    uint32_t par[2][kParWords];     // bit a of par[p] = b_{2a+p} (0 past the sequence end)
+    uint32_t rev[2][kRevWords];     // bit a of rev[p] = bit (kNA-1-a) of par[p], 0 past kNA-1
+    uint32_t xw[kXWords];           // free bits (kept current by every commit)
+    uint32_t bestx[kXWords];        // free bits of the best state of the walk so far
+    int32_t C[kMfmaCWords];         // C'_kappa at index kappa
+    uint32_t sb[4][kMfmaSeqStride]; // +-1 byte copies of the A strings (first kMfmaSeqDwords used)
     uint32_t cb[4][kMfmaCDwords];   // C' as int8, four copies shifted by 0..3 bytes
 };
 
@@ -48,10 +65,12 @@ __device__ __forceinline__ uint32_t nibble_bytes(uint32_t nib)
     return (nib * 0x00204081u) & 0x01010101u;
 }
 
-__device__ __forceinline__ uint32_t alignbyte(uint32_t hi, uint32_t lo, uint32_t sh)
-{
-    return __builtin_amdgcn_alignbyte(hi, lo, sh);
-}
+// Per-lane constants of one owned flip (they depend only on L and j).
+struct MfmaFlip {
+    const int32_t *c_kd; // C'_{kappa_d}; the zero word C'_c for the centre (and past it)
+    uint32_t m0, m1;     // both-sided shifts but kappa_d: bits kappa < nq, kappa != kappa_d
+    int32_t hc;          // np + 3 nq - 1 - 2 [q_d valid]; nq for the centre
+};
 
 template <int KW>
 struct MfmaWalker {
@@ -65,45 +84,62 @@ struct MfmaWalker {
     int lane;
     int32_t isl;
     uint64_t h;
-    uint32_t x[kXWords];
+    uint32_t x[kXWords]; // free bits; current only where commit<true> is used (else in lds->xw)
+    uint32_t x0;         // free bits 0..31, always current
     int32_t Cv[QR];
-    int32_t sbit[G];
+    int32_t mult[G];     // factor of T_j: -8 s_j (-4 s_c for the centre, 0 past it)
     int planes;
+    int32_t eps8[G];     // 8 (-1)^(c-j) for j of parity g (uniform)
     Lds *lds;
     const uint64_t *zk;
-    FlipConst fc[G];
+    MfmaFlip fc[G];
 
     __device__ __forceinline__ int flip(int g) const { return 2 * lane + g; }
+
+    __device__ __forceinline__ uint32_t *x_lds() const { return lds->xw; }
+    __device__ __forceinline__ uint32_t *best_lds() const { return lds->bestx; }
+
+    // b_js (uniform) from the lane that scores flip js: mult > 0 iff s_js = -1
+    __device__ __forceinline__ uint32_t sbit_of(int js) const
+    {
+        const int32_t v0 = __builtin_amdgcn_readlane(mult[0], js >> 1);
+        const int32_t v1 = __builtin_amdgcn_readlane(mult[1], js >> 1);
+        return ((js & 1) ? v1 : v0) > 0 ? 1u : 0u;
+    }
 
     __device__ __forceinline__ void set_length(int len)
     {
         L = len;
         c = (L - 1) / 2;
         n = c + 1;
+        eps8[0] = (c & 1) ? -8 : 8;
+        eps8[1] = -eps8[0];
     }
 
     __device__ __forceinline__ void init_lanes(int ln)
     {
 #pragma unroll
         for (int g = 0; g < G; g++) {
-            const int j = min(2 * ln + g, c);
-            const int p = j & 1, hj = j >> 1;
-            const int nq = hj;
+            const int j = 2 * ln + g;
+            const int nq = ln;
             const int np = c - ((j + 1) >> 1);
-            FlipConst &f = fc[g];
-            f.sp = (uint32_t)(hj + 1);
-            f.wp = &lds->par[p][(hj + 1) >> 5];
-            f.wq = &lds->rev[p][(kNA - hj) >> 5];
-            f.psx_np = &lds->psx[np];
-            f.psx_nq = &lds->psx[nq];
-            f.c_kd = &lds->C[max(c - 1 - j, 0)];
-            const int iq = 3 * j - 2 * c;
-            const int a = max(iq, 0) >> 1;
-            f.qd_word = &lds->par[p][a >> 5];
-            f.qd_shift = (uint32_t)(a & 31);
-            f.m_par = (uint32_t)((c - j) & 1);
-            f.hconst = np + 3 * nq - 1;
-            f.nq = nq;
+            MfmaFlip &f = fc[g];
+            if (j < c) {
+                const int kd = c - 1 - j;
+                const bool qdv = kd < nq;
+                uint64_t m = (1ull << nq) - 1ull; // nq <= 63
+                if (qdv)
+                    m &= ~(1ull << kd);
+                f.c_kd = &lds->C[kd];
+                f.m0 = (uint32_t)m;
+                f.m1 = (uint32_t)(m >> 32);
+                f.hc = np + 3 * nq - 1 - (qdv ? 2 : 0);
+            } else {
+                f.c_kd = &lds->C[c];
+                f.m0 = 0u;
+                f.m1 = 0u;
+                f.hc = nq;
+            }
         }
     }
 
@@ -119,6 +155,7 @@ struct MfmaWalker {
     __device__ __forceinline__ void rebuild()
     {
         const int lane = this->lane;
+        x0 = x[0];
         if (lane == 0) {
 #pragma unroll
             for (int w = 0; w < kXWords; w++)
@@ -147,20 +184,34 @@ struct MfmaWalker {
             lds->rev[lane & 1][6 + (lane >> 1)] = 0u;
         for (int i = lane; i < 4 * kMfmaCDwords; i += kWave)
             lds->cb[i / kMfmaCDwords][i % kMfmaCDwords] = 0u;
+        // prepare() writes C'_kappa for kappa < 64 QR; the zero word C'_c may lie past that (c = 64)
+        for (int i = lane; i < kMfmaCWords; i += kWave)
+            lds->C[i] = 0;
         lds_fence();
-        // byte copies of the strings: kind p from par[p] at bit u, kind 2+p from rev[p] at bit
-        // 128 + u (= b^p_{63-u}, zero past u = 63)
+        // +-1 byte copies of the strings: kind p from par[p] at half index u = 4 lane + i, kind
+        // 2+p from rev[p] at bit 128 + u (= s^p_{63-u}); 0 where the half index is outside the
+        // sequence (2 u' + p > L - 1, or u' < 0)
 #pragma unroll
         for (int k4 = 0; k4 < 4; k4++) {
             const int p = k4 & 1;
             const int bitpos = (k4 < 2 ? 0 : 128) + 4 * lane;
             const uint32_t word = (k4 < 2) ? lds->par[p][bitpos >> 5] : lds->rev[p][bitpos >> 5];
-            lds->sb[k4][lane] = nibble_bytes((word >> (bitpos & 31)) & 0xFu);
+            uint32_t valid = 0;
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int u = (k4 < 2) ? 4 * lane + i : 63 - (4 * lane + i);
+                valid |= (u >= 0 && 2 * u + p <= L - 1) ? 1u << i : 0u;
+            }
+            const uint32_t bits = (word >> (bitpos & 31)) & valid;
+            lds->sb[k4][lane] = nibble_bytes(valid) | (nibble_bytes(bits) * 0xFEu);
         }
+        uint32_t sb2[G];
 #pragma unroll
         for (int g = 0; g < G; g++) {
             const int j = 2 * lane + g;
-            sbit[g] = (j <= c) ? (int32_t)seq_bit(j) : 0;
+            sb2[g] = (j <= c) ? seq_bit(j) : 0u;
+            const int32_t s = 1 - 2 * (int32_t)sb2[g];
+            mult[g] = j < c ? -8 * s : (j == c ? -4 * s : 0);
         }
         int32_t sq = 0;
 #pragma unroll
@@ -192,30 +243,24 @@ struct MfmaWalker {
 #pragma unroll
         for (int g = 0; g < G; g++) {
             const int j = 2 * lane + g;
-            if (j <= c && sbit[g])
+            if (j <= c && sb2[g])
                 hz ^= zk[j];
         }
         h = wave_xor_u64(hz);
         lds_fence();
     }
 
-    // C to LDS, prefix sums, whether C' fits int8; C' bytes for the B operand.
+    // C' to LDS (for the excluded-shift term), whether C' fits int8, and C' bytes for the B
+    // operand.
     __device__ __forceinline__ void prepare()
     {
         const int lane = this->lane;
-        int32_t running = 0;
         bool wide = false; // some |C_k| above the int8 range
 #pragma unroll
         for (int q = 0; q < QR; q++) {
-            const int kappa = lane + 64 * q;
-            lds->C[kappa] = Cv[q];
-            const int32_t inc = wave_inclusive_scan(Cv[q]) + running;
-            lds->psx[kappa + 1] = inc;
-            running = readlane_i(inc, 63);
+            lds->C[lane + 64 * q] = Cv[q];
             wide = wide || (uint32_t)(Cv[q] + 128) > 255u;
         }
-        if (lane == 0)
-            lds->psx[0] = 0;
         planes = ballot(wide) != 0ull ? 9 : 8; // only "fits int8 or not" is used
         put_c(planes <= 8 ? 0 : 1); // C' itself, or its low six bits (the high part follows later)
         lds_fence();
@@ -237,21 +282,20 @@ struct MfmaWalker {
 
     // One K-sweep of the tile with the C' bytes now in the copies.  Lane (slice, nn) needs the
     // 16 bytes C'_{i0 .. i0+15}, i0 = t0 - 1 - nn; copy r = (i0 + 20) mod 4 holds them from a
-    // dword boundary.
+    // dword boundary.  Successive K blocks are 16 dwords further in both operands.
     __device__ __forceinline__ mfma_v4i tile() const
     {
         const int lane = this->lane;
         const int nn = lane & 15, slice = lane >> 4;
         const int kind = lane & 3, ib = (lane & 15) >> 2;
         const int r = (3 - nn) & 3;
+        const uint32_t *ap = &lds->sb[kind][4 * (slice + ib)];
+        const uint32_t *bp = &lds->cb[r][(16 * slice - 1 - nn + 20 - r) >> 2];
         mfma_v4i acc = {0, 0, 0, 0};
 #pragma unroll
         for (int kb = 0; kb < KB; kb++) {
-            const int t0 = 16 * slice + 64 * kb;
-            const uint32_t *ap = &lds->sb[kind][(t0 + 16 * ib) >> 2];
-            const mfma_v4i a = {(int)ap[0], (int)ap[1], (int)ap[2], (int)ap[3]};
-            const uint32_t *bp = &lds->cb[r][(t0 - 1 - nn + 20 - r) >> 2];
-            const mfma_v4i b = {(int)bp[0], (int)bp[1], (int)bp[2], (int)bp[3]};
+            const mfma_v4i a = {(int)ap[16 * kb], (int)ap[16 * kb + 1], (int)ap[16 * kb + 2], (int)ap[16 * kb + 3]};
+            const mfma_v4i b = {(int)bp[16 * kb], (int)bp[16 * kb + 1], (int)bp[16 * kb + 2], (int)bp[16 * kb + 3]};
             acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc, 0, 0, 0);
         }
         return acc;
@@ -271,40 +315,34 @@ struct MfmaWalker {
         }
         // Z for h = lane sits in lane 63 - lane
         const int src = (63 - lane) << 2;
-        int32_t acc[G];
-        acc[0] = d[0] + __builtin_amdgcn_ds_bpermute(src, d[2]);
-        acc[1] = d[1] + __builtin_amdgcn_ds_bpermute(src, d[3]);
+        int32_t T[G];
+        T[0] = d[0] + __builtin_amdgcn_ds_bpermute(src, d[2]);
+        T[1] = d[1] + __builtin_amdgcn_ds_bpermute(src, d[3]);
+        // window words of the both-sided shifts kappa < nq = lane <= 63: p window from bit h+1 of
+        // par[g], q window from bit kNA-h of rev[g]
+        const uint32_t sp = (uint32_t)(lane + 1);
+        const uint32_t *wp = &lds->par[0][(lane + 1) >> 5];
+        const uint32_t *wq = &lds->rev[0][(kNA - lane) >> 5];
 #pragma unroll
         for (int g = 0; g < G; g++) {
-            const FlipConst &f = fc[g];
-            // R_j = nq - 2 rc, rc = differing bits of Wp and Wq over the both-sided shifts
-            // (kappa < nq <= 63: two window words)
-            const uint32_t wp0 = funnel(f.wp[1], f.wp[0], (int)f.sp);
-            const uint32_t wp1 = funnel(f.wp[2], f.wp[1], (int)f.sp);
-            const uint32_t wq0 = funnel(f.wq[1], f.wq[0], (int)(1u - f.sp));
-            const uint32_t wq1 = funnel(f.wq[2], f.wq[1], (int)(1u - f.sp));
-            uint32_t rc = bcnt_acc((wp0 ^ wq0) & low_mask(f.nq), 0u);
-            rc = bcnt_acc((wp1 ^ wq1) & low_mask(f.nq - 32), rc);
-            const int32_t Cd = *f.c_kd;
-            const int32_t pnp = *f.psx_np, pnq = *f.psx_nq;
-            const uint32_t qbit = (*f.qd_word >> f.qd_shift) & 1u;
-            const uint32_t m_neg = (uint32_t)sbit[g] ^ f.m_par;
-            const int j = 2 * lane + g;
-            const bool centre = j == c;
-            const bool qd_valid = 3 * j >= 2 * c;
-            const int32_t smqd = qd_valid ? ((m_neg ^ qbit) ? -1 : 1) : 0;
-            const int32_t Gg = pnp + pnq - 2 * acc[g] - (m_neg ? -Cd : Cd);
-            const int32_t Hg = f.hconst - 4 * (int32_t)rc - 2 * smqd;
-            const int32_t Gj = centre ? pnq - acc[g] : Gg;
-            const int32_t Hj = centre ? f.nq : Hg;
-            isl_j[g] = isl + (sbit[g] ? 8 * Gj : -8 * Gj) + 16 * Hj;
+            const MfmaFlip &f = fc[g];
+            const uint32_t *wpg = wp + g * kParWords;
+            const uint32_t *wqg = wq + g * kRevWords;
+            const uint32_t wp0 = funnel(wpg[1], wpg[0], (int)sp);
+            const uint32_t wp1 = funnel(wpg[2], wpg[1], (int)sp);
+            const uint32_t wq0 = funnel(wqg[1], wqg[0], (int)(1u - sp));
+            const uint32_t wq1 = funnel(wqg[2], wqg[1], (int)(1u - sp));
+            uint32_t rc = bcnt_acc((wp0 ^ wq0) & f.m0, 0u);
+            rc = bcnt_acc((wp1 ^ wq1) & f.m1, rc);
+            isl_j[g] = isl + 16 * f.hc - 64 * (int32_t)rc + eps8[g] * *f.c_kd + mult[g] * T[g];
         }
     }
 
+    template <bool REG_X = true>
     __device__ __forceinline__ void commit(int js, int32_t isl_new)
     {
         const int lane = this->lane;
-        const int32_t sjs = 1 - 2 * (int32_t)xbit_uniform(x, js);
+        const int32_t sjs = 1 - 2 * (int32_t)(REG_X ? xbit_uniform(x, js) : sbit_of(js));
         const int hjs = js >> 1;
         const int pis = js & 1;
         const int nps = (js == c) ? 0 : c - ((js + 1) >> 1);
@@ -325,25 +363,30 @@ struct MfmaWalker {
         }
         lds_fence();
         // the flipped symbol and its mirror (m = 2c - js, half index nps) in the bit strings and
-        // in the byte copies (kind p at byte a, kind 2+p at byte 63 - a when a <= 63)
+        // in the +-1 byte copies (kind p at byte a, kind 2+p at byte 63 - a when a <= 63; 0x01 and
+        // 0xFF swap under xor 0xFE)
         if (lane < 4 && ((lane & 1) == 0 || js != c)) {
             const int a = (lane & 1) ? nps : hjs;
             if (lane < 2) {
                 atomicXor(&lds->par[pis][a >> 5], 1u << (a & 31));
                 const int ar = kNA - 1 - a;
                 atomicXor(&lds->rev[pis][ar >> 5], 1u << (ar & 31));
-                atomicXor(&lds->sb[pis][a >> 2], 1u << (8 * (a & 3)));
+                atomicXor(&lds->sb[pis][a >> 2], 0xFEu << (8 * (a & 3)));
+                if (lane == 0) // the free bit itself
+                    atomicXor(&lds->xw[js >> 5], 1u << (js & 31));
             } else {
                 const int u = 63 - a;
                 if (u >= 0)
-                    atomicXor(&lds->sb[2 + pis][u >> 2], 1u << (8 * (u & 3)));
+                    atomicXor(&lds->sb[2 + pis][u >> 2], 0xFEu << (8 * (u & 3)));
             }
         }
         lds_fence();
 #pragma unroll
         for (int g = 0; g < G; g++)
-            sbit[g] ^= (2 * lane + g == js) ? 1 : 0;
-        xflip_uniform(x, js);
+            mult[g] = (2 * lane + g == js) ? -mult[g] : mult[g];
+        if (REG_X)
+            xflip_uniform(x, js);
+        x0 ^= js < 32 ? 1u << js : 0u;
         const uint64_t z = zk[js];
         h ^= ((uint64_t)uniform((uint32_t)(z >> 32)) << 32) | uniform((uint32_t)z);
         isl = isl_new;

@@ -44,7 +44,8 @@ constexpr int kSeqBytes = 1280; // zero padding on both sides covers every j +- 
 struct WaveLdsBits {
     uint32_t par[2][kParWords]; // bit a of par[p] = b_{2a+p} (0 past the sequence end)
     uint32_t rev[2][kRevWords]; // bit a of rev[p] = bit (kNA-1-a) of par[p], 0 past kNA-1
-    uint32_t xw[kXWords];       // free bits
+    uint32_t xw[kXWords];       // free bits (kept current by every commit)
+    uint32_t bestx[kXWords];    // free bits of the best state of the walk so far
     int32_t C[kCMax + 1];       // C_{2 kappa + 2} at index kappa (0 for kappa >= c)
     int32_t psx[kCMax + 2];     // psx[a] = sum_{kappa < a} C
 };
@@ -128,7 +129,8 @@ struct Walker {
     int lane; // lane id, laundered every step so that lane-derived values are recomputed
     int32_t isl;
     uint64_t h;
-    uint32_t x[kXWords];
+    uint32_t x[kXWords]; // free bits; current only where commit<true> is used (else in lds->xw)
+    uint32_t x0;         // free bits 0..31, always current (they address the exact table)
     int32_t Cv[QR];
     int32_t sbit[G];
     int planes;
@@ -145,6 +147,20 @@ struct Walker {
 
     // flip scored in slot g of this lane
     __device__ __forceinline__ int flip(int g) const { return lane + 64 * g; }
+
+    // LDS copies of the current and of the best free bits
+    __device__ __forceinline__ uint32_t *x_lds() const { return lds->xw; }
+    __device__ __forceinline__ uint32_t *best_lds() const { return lds->bestx; }
+
+    // b_js (uniform) from the lane that scores flip js
+    __device__ __forceinline__ uint32_t sbit_of(int js) const
+    {
+        uint32_t v = 0;
+#pragma unroll
+        for (int g = 0; g < G; g++)
+            v = (g == (js >> 6)) ? (uint32_t)__builtin_amdgcn_readlane(sbit[g], js & 63) : v;
+        return v;
+    }
 
     __device__ __forceinline__ void init_lanes(int ln)
     {
@@ -193,6 +209,7 @@ struct Walker {
     __device__ __forceinline__ void rebuild()
     {
         const int lane = this->lane;
+        x0 = x[0];
         if (lane == 0) {
 #pragma unroll
             for (int w = 0; w < kXWords; w++)
@@ -444,11 +461,13 @@ struct Walker {
         }
     }
 
-    // Commit flip js (uniform): update C_k by dC_k, the bit strings / sequence, x and the hash.
+    // Commit flip js (uniform): update C_k by dC_k, the bit strings / sequence, the free bits
+    // (lds->xw and x0; the register copy x as well when REG_X) and the hash.
+    template <bool REG_X = true>
     __device__ __forceinline__ void commit(int js, int32_t isl_new)
     {
         const int lane = this->lane;
-        const int32_t sjs = 1 - 2 * (int32_t)xbit_uniform(x, js);
+        const int32_t sjs = 1 - 2 * (int32_t)(REG_X ? xbit_uniform(x, js) : sbit_of(js));
         const int hjs = js >> 1;
         const int pis = js & 1;
         const int nps = (js == c) ? 0 : c - ((js + 1) >> 1);
@@ -474,6 +493,8 @@ struct Walker {
             }
         }
         lds_fence();
+        if (lane == 2)
+            atomicXor(&lds->xw[js >> 5], 1u << (js & 31));
         if constexpr (!DIRECT) {
             if (lane < 2 && (lane == 0 || js != c)) {
                 const int a = (lane == 0) ? hjs : nps; // mirror m = 2c - js has a = nps
@@ -491,7 +512,9 @@ struct Walker {
 #pragma unroll
         for (int g = 0; g < G; g++)
             sbit[g] ^= (lane + 64 * g == js) ? 1 : 0;
-        xflip_uniform(x, js);
+        if (REG_X)
+            xflip_uniform(x, js);
+        x0 ^= js < 32 ? 1u << js : 0u;
         const uint64_t z = zk[js];
         h ^= ((uint64_t)uniform((uint32_t)(z >> 32)) << 32) | uniform((uint32_t)z);
         isl = isl_new;
@@ -558,7 +581,10 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
 
     int64_t t, flips, hit, wstep, best_isl, best_step;
     int32_t restart_idx, restarts, traps;
-    uint32_t best_x[kXWords];
+    // The free bits live in LDS during the walk (the walker's x_lds(), and best_lds() for the
+    // best state), so that the hot loop keeps none of them in scalar registers.
+    uint32_t *const xl = w.x_lds();
+    uint32_t *const bl = w.best_lds();
 
     if (status0 == kFresh) {
         restart_idx = 0;
@@ -566,24 +592,23 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
         clear_table(T, tlog2);
         w.rebuild();
         if (lane == 0)
-            T[slot_of(w.h, w.x[0], exact, tlog2)] = w.h | 1ull;
+            T[slot_of(w.h, w.x0, exact, tlog2)] = w.h | 1ull;
         t = 0;
         flips = 0;
         restarts = 0;
         traps = 0;
         best_isl = w.isl;
         best_step = 0;
-#pragma unroll
-        for (int i = 0; i < kXWords; i++)
-            best_x[i] = w.x[i];
+        if (lane < kXWords)
+            bl[lane] = xl[lane];
         hit = (target >= 0 && w.isl <= target) ? 0 : -1;
         wstep = (watch >= 0 && w.isl <= watch) ? 0 : -1;
     } else {
 #pragma unroll
-        for (int i = 0; i < kXWords; i++) {
+        for (int i = 0; i < kXWords; i++)
             w.x[i] = su(ws.x[i]);
-            best_x[i] = su(ws.best_x[i]);
-        }
+        if (lane < kXWords)
+            bl[lane] = ws.best_x[lane];
         restart_idx = su(ws.restart_idx);
         restarts = su(ws.restarts);
         traps = su(ws.traps);
@@ -613,8 +638,20 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
     int32_t rem = (R > 0) ? (int32_t)min<int64_t>((t0 / R + 1) * R - t0, INT32_MAX) : INT32_MAX;
     bool hit_found = hit >= 0;
     bool watch_found = wstep >= 0;
-    bool stop = tgt >= 0 && hit_found;
     int32_t best32 = (int32_t)best_isl;
+    // the step loop runs while ts < lim; reaching the target sets lim = ts
+    int32_t lim = (tgt >= 0 && hit_found) ? 0 : nsteps;
+    // A committed state needs the bookkeeping below only if its ISL is at most thr: a new best,
+    // or the target or watch level not reached before.
+    auto threshold = [&]() -> int32_t {
+        int32_t v = best32 - 1;
+        if (tgt >= 0 && !hit_found)
+            v = max(v, tgt);
+        if (wch >= 0 && !watch_found)
+            v = max(v, wch);
+        return v;
+    };
+    int32_t thr = threshold();
     // steps of this launch at which best / hit / watch were reached (-1 = not in this launch)
     int32_t best_ts = -1, hit_ts = -1, watch_ts = -1;
     // steps left before the budget, as seen from this launch (periodic restarts stop there)
@@ -636,14 +673,14 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
             clear_table(T, tlog2);
             w.rebuild();
             if (lane == 0)
-                T[slot_of(w.h, w.x[0], exact, tlog2)] = w.h | 1ull;
+                T[slot_of(w.h, w.x0, exact, tlog2)] = w.h | 1ull;
             if (trap_trp && lane == 0) {
                 trap_trp[0] = -1;
                 trap_trp[1] = w.isl;
             }
             trap_trp = nullptr;
         }
-        while (ts < nsteps && !stop) {
+        while (ts < lim) {
             // Keep per-lane index arithmetic inside the loop instead of pinning ~100 VGPRs of
             // loop invariants for the whole walk: the values are cheap to recompute and the
             // registers are worth more as occupancy.
@@ -687,9 +724,7 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
                     my = (w.lane == i) ? cand[i] : my;
                 const int jm = min((int)(my & 255u), n - 1);
                 const uint64_t hc = w.h ^ zk[jm];
-                uint32_t x0 = w.x[0] ^ (1u << (jm & 31));
-                if (jm >= 32)
-                    x0 = w.x[0];
+                const uint32_t x0 = w.x0 ^ (jm < 32 ? 1u << (jm & 31) : 0u);
                 uint64_t got = 0;
                 if (w.lane < PW && my != 0xFFFFFFFFu)
                     got = T[slot_of(hc, x0, exact, tlog2)];
@@ -725,9 +760,9 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
                 need_restart = true;
                 break;
             }
-            w.commit(js, isl_new);
+            w.template commit<false>(js, isl_new);
             if (w.lane == 0)
-                T[slot_of(w.h, w.x[0], exact, tlog2)] = w.h | 1ull;
+                T[slot_of(w.h, w.x0, exact, tlog2)] = w.h | 1ull;
             if (trp) {
                 if (w.lane == 0) {
                     trp[0] = js;
@@ -737,26 +772,28 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
             }
             if (scp)
                 scp += n;
-            if (w.isl < best32) {
-                best32 = w.isl;
-                best_ts = ts;
-#pragma unroll
-                for (int i = 0; i < kXWords; i++)
-                    best_x[i] = w.x[i];
-            }
-            if (tgt >= 0 && !hit_found && w.isl <= tgt) {
-                hit_found = true;
-                hit_ts = ts;
-                stop = true;
-            }
-            if (wch >= 0 && !watch_found && w.isl <= wch) {
-                watch_found = true;
-                watch_ts = ts;
+            if (w.isl <= thr) {
+                if (w.isl < best32) {
+                    best32 = w.isl;
+                    best_ts = ts;
+                    if (w.lane < kXWords)
+                        bl[w.lane] = xl[w.lane];
+                }
+                if (tgt >= 0 && !hit_found && w.isl <= tgt) {
+                    hit_found = true;
+                    hit_ts = ts;
+                    lim = ts;
+                }
+                if (wch >= 0 && !watch_found && w.isl <= wch) {
+                    watch_found = true;
+                    watch_ts = ts;
+                }
+                thr = threshold();
             }
             if (rem == 0) {
                 rem = R32;
                 // periodic restart (not after the last step, not once stopped)
-                if (ts < left32 && !stop) {
+                if (ts < left32 && !(tgt >= 0 && hit_found)) {
                     need_restart = true;
                     break;
                 }
@@ -775,6 +812,11 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
     if (watch_ts >= 0)
         wstep = t0 + watch_ts;
 
+    lds_fence();
+    if (lane < kXWords) {
+        ws.x[lane] = xl[lane];
+        ws.best_x[lane] = bl[lane];
+    }
     if (lane == 0) {
         ws.t = t;
         ws.flips = flips;
@@ -787,11 +829,6 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
         ws.restart_idx = restart_idx;
         ws.restarts = restarts;
         ws.traps = traps;
-#pragma unroll
-        for (int i = 0; i < kXWords; i++) {
-            ws.x[i] = w.x[i];
-            ws.best_x[i] = best_x[i];
-        }
         ws.status = (t >= steps || (target >= 0 && hit >= 0)) ? kDone : kRunning;
     }
     (void)L;
