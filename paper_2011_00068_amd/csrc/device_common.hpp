@@ -160,4 +160,21 @@ __device__ inline uint32_t bcnt_acc(uint32_t x, uint32_t acc)
     return r;
 }
 
+// a * b + acc for a, b in the signed 24-bit range, as one full-rate v_mad_i32_i24 (the generic
+// 32-bit multiply is a multi-pass instruction).
+__device__ inline int32_t mad24(int32_t a, int32_t b, int32_t acc)
+{
+    int32_t r;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(acc));
+    return r;
+}
+
+// the same with a wave-uniform b
+__device__ inline int32_t mad24_u(int32_t a, int32_t b, int32_t acc)
+{
+    int32_t r;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(acc));
+    return r;
+}
+
 } // namespace liblabs

@@ -41,6 +41,8 @@
 namespace liblabs {
 
 typedef int mfma_v4i __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) const uint32_t lds_cu32; // LDS words, read
+typedef __attribute__((address_space(3))) const uint64_t lds_cu64; // (8-byte aligned) LDS pairs, read
 
 constexpr int kMfmaSeqDwords = 64; // 256 bytes per string copy
 constexpr int kMfmaSeqStride = 66; // copies 2 dwords apart in bank order: the four copies read by one
@@ -93,6 +95,9 @@ struct MfmaWalker {
     Lds *lds;
     const uint64_t *zk;
     MfmaFlip fc[G];
+    uint32_t ta, tb; // LDS addresses of this lane's A and B words of K block 0 (see init_lanes())
+    uint32_t wpa, wqa; // LDS addresses of the first window words of par[0] and rev[0] (see score())
+    int32_t bsrc;      // ds_bpermute source of Z: lane 63 - lane
 
     __device__ __forceinline__ int flip(int g) const { return 2 * lane + g; }
 
@@ -118,6 +123,23 @@ struct MfmaWalker {
 
     __device__ __forceinline__ void init_lanes(int ln)
     {
+        {
+            // Lane (slice, nn) of the tile needs A bytes S_kind[t0 + 16 ib ..] and the 16 bytes
+            // C'_{i0 .. i0+15}, i0 = t0 - 1 - nn, t0 = 16 slice + 64 kb; copy r = (i0 + 20) mod 4 of
+            // C' holds them from a dword boundary.  K block kb is 16 dwords further in both.
+            const int nn = ln & 15, slice = ln >> 4;
+            const int kind = ln & 3, ib = (ln & 15) >> 2;
+            const int r = (3 - nn) & 3;
+            ta = (uint32_t)(uintptr_t)&lds->sb[kind][4 * (slice + ib)];
+            tb = (uint32_t)(uintptr_t)&lds->cb[r][(16 * slice - 1 - nn + 20 - r) >> 2];
+            // window words of the both-sided shifts kappa < nq = ln <= 63: the p window starts at
+            // bit h+1 of par[g], the q window at bit kNA-h of rev[g]
+            wpa = (uint32_t)(uintptr_t)&lds->par[0][(ln + 1) >> 5];
+            wqa = (uint32_t)(uintptr_t)&lds->rev[0][(kNA - ln) >> 5];
+            bsrc = (63 - ln) << 2;
+            // whole addresses, so that every load is one base register plus an offset
+            asm volatile("" : "+v"(ta), "+v"(tb), "+v"(wpa), "+v"(wqa), "+v"(bsrc));
+        }
 #pragma unroll
         for (int g = 0; g < G; g++) {
             const int j = 2 * ln + g;
@@ -262,7 +284,9 @@ struct MfmaWalker {
             wide = wide || (uint32_t)(Cv[q] + 128) > 255u;
         }
         planes = ballot(wide) != 0ull ? 9 : 8; // only "fits int8 or not" is used
-        put_c(planes <= 8 ? 0 : 1); // C' itself, or its low six bits (the high part follows later)
+        put_c(0);
+        if (planes > 8)
+            put_c(1); // C' does not fit: its low six bits first (the high part follows in score())
         lds_fence();
     }
 
@@ -280,30 +304,53 @@ struct MfmaWalker {
         }
     }
 
-    // One K-sweep of the tile with the C' bytes now in the copies.  Lane (slice, nn) needs the
-    // 16 bytes C'_{i0 .. i0+15}, i0 = t0 - 1 - nn; copy r = (i0 + 20) mod 4 holds them from a
-    // dword boundary.  Successive K blocks are 16 dwords further in both operands.
+    // One K-sweep of the tile with the C' bytes now in the copies.
     __device__ __forceinline__ mfma_v4i tile() const
     {
-        const int lane = this->lane;
-        const int nn = lane & 15, slice = lane >> 4;
-        const int kind = lane & 3, ib = (lane & 15) >> 2;
-        const int r = (3 - nn) & 3;
-        const uint32_t *ap = &lds->sb[kind][4 * (slice + ib)];
-        const uint32_t *bp = &lds->cb[r][(16 * slice - 1 - nn + 20 - r) >> 2];
-        mfma_v4i acc = {0, 0, 0, 0};
+        // A windows start on 8-byte boundaries (the string copies are 264 bytes apart), B windows on
+        // dword boundaries
+        const lds_cu64 *ap = (const lds_cu64 *)(uintptr_t)ta;
+        const lds_cu32 *bp = (const lds_cu32 *)(uintptr_t)tb;
+        // every operand load first, so that one LDS latency covers the whole K sweep
+        mfma_v4i a[KB], b[KB];
 #pragma unroll
         for (int kb = 0; kb < KB; kb++) {
-            const mfma_v4i a = {(int)ap[16 * kb], (int)ap[16 * kb + 1], (int)ap[16 * kb + 2], (int)ap[16 * kb + 3]};
-            const mfma_v4i b = {(int)bp[16 * kb], (int)bp[16 * kb + 1], (int)bp[16 * kb + 2], (int)bp[16 * kb + 3]};
-            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc, 0, 0, 0);
+            const uint64_t a0 = ap[8 * kb], a1 = ap[8 * kb + 1];
+            a[kb] = mfma_v4i{(int)(uint32_t)a0, (int)(uint32_t)(a0 >> 32), (int)(uint32_t)a1, (int)(uint32_t)(a1 >> 32)};
+            b[kb] = mfma_v4i{(int)bp[16 * kb], (int)bp[16 * kb + 1], (int)bp[16 * kb + 2], (int)bp[16 * kb + 3]};
         }
+        mfma_v4i acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int kb = 0; kb < KB; kb++)
+            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[kb], b[kb], acc, 0, 0, 0);
         return acc;
     }
 
     __device__ __forceinline__ void score(int32_t (&isl_j)[G])
     {
         const int lane = this->lane;
+        // the part without T first (bit-string and table reads that do not wait for the tile):
+        // base_j = ISL + 16 hc - 64 rc' + 8 (-1)^(c-j) C'_{kappa_d}
+        int32_t base[G];
+        {
+            const uint32_t sp = (uint32_t)(lane + 1); // window shifts: h+1 and kNA-h = 1 - sp (mod 32)
+            const lds_cu32 *wp = (const lds_cu32 *)(uintptr_t)wpa;
+            const lds_cu32 *wq = (const lds_cu32 *)(uintptr_t)wqa;
+#pragma unroll
+            for (int g = 0; g < G; g++) {
+                const MfmaFlip &f = fc[g];
+                const lds_cu32 *wpg = wp + g * kParWords;
+                const lds_cu32 *wqg = wq + g * kRevWords;
+                const uint32_t wp0 = funnel(wpg[1], wpg[0], (int)sp);
+                const uint32_t wp1 = funnel(wpg[2], wpg[1], (int)sp);
+                const uint32_t wq0 = funnel(wqg[1], wqg[0], (int)(1u - sp));
+                const uint32_t wq1 = funnel(wqg[2], wqg[1], (int)(1u - sp));
+                uint32_t rc = bcnt_acc((wp0 ^ wq0) & f.m0, 0u);
+                rc = bcnt_acc((wp1 ^ wq1) & f.m1, rc);
+                // |C'| <= 253: a 24-bit product
+                base[g] = isl + 16 * f.hc - 64 * (int32_t)rc + __mul24(eps8[g], *f.c_kd);
+            }
+        }
         mfma_v4i d = tile();
         if (planes > 8) {
             // C' = 64 hi + lo: the copies held lo; the wave's LDS operations run in order, so the
@@ -313,53 +360,30 @@ struct MfmaWalker {
             const mfma_v4i hi = tile();
             d = d + hi * 64;
         }
-        // Z for h = lane sits in lane 63 - lane
-        const int src = (63 - lane) << 2;
-        int32_t T[G];
-        T[0] = d[0] + __builtin_amdgcn_ds_bpermute(src, d[2]);
-        T[1] = d[1] + __builtin_amdgcn_ds_bpermute(src, d[3]);
-        // window words of the both-sided shifts kappa < nq = lane <= 63: p window from bit h+1 of
-        // par[g], q window from bit kNA-h of rev[g]
-        const uint32_t sp = (uint32_t)(lane + 1);
-        const uint32_t *wp = &lds->par[0][(lane + 1) >> 5];
-        const uint32_t *wq = &lds->rev[0][(kNA - lane) >> 5];
-#pragma unroll
-        for (int g = 0; g < G; g++) {
-            const MfmaFlip &f = fc[g];
-            const uint32_t *wpg = wp + g * kParWords;
-            const uint32_t *wqg = wq + g * kRevWords;
-            const uint32_t wp0 = funnel(wpg[1], wpg[0], (int)sp);
-            const uint32_t wp1 = funnel(wpg[2], wpg[1], (int)sp);
-            const uint32_t wq0 = funnel(wqg[1], wqg[0], (int)(1u - sp));
-            const uint32_t wq1 = funnel(wqg[2], wqg[1], (int)(1u - sp));
-            uint32_t rc = bcnt_acc((wp0 ^ wq0) & f.m0, 0u);
-            rc = bcnt_acc((wp1 ^ wq1) & f.m1, rc);
-            isl_j[g] = isl + 16 * f.hc - 64 * (int32_t)rc + eps8[g] * *f.c_kd + mult[g] * T[g];
-        }
+        // Z for h = lane sits in lane 63 - lane; |T| <= 128 * 253: a 24-bit product
+        isl_j[0] = mad24(mult[0], d[0] + __builtin_amdgcn_ds_bpermute(bsrc, d[2]), base[0]);
+        isl_j[1] = mad24(mult[1], d[1] + __builtin_amdgcn_ds_bpermute(bsrc, d[3]), base[1]);
     }
 
     template <bool REG_X = true>
     __device__ __forceinline__ void commit(int js, int32_t isl_new)
     {
         const int lane = this->lane;
-        const int32_t sjs = 1 - 2 * (int32_t)(REG_X ? xbit_uniform(x, js) : sbit_of(js));
+        const uint32_t bjs = REG_X ? xbit_uniform(x, js) : sbit_of(js);
         const int hjs = js >> 1;
         const int pis = js & 1;
         const int nps = (js == c) ? 0 : c - ((js + 1) >> 1);
         const int kds = (js == c) ? -1 : c - 1 - js;
+        // dC'_kappa = -4 s_js (p_kappa + q_kappa), p without the excluded shift kappa_d, read from
+        // the +-1 byte strings (0 past either end, so lanes with kappa >= c add nothing); at the
+        // centre p = q and u = q, so the factor is halved instead
+        const int32_t f = (js == c) ? (bjs ? 2 : -2) : (bjs ? 4 : -4);
+        const int8_t *pb = reinterpret_cast<const int8_t *>(lds->sb[pis]) + hjs + 1 + lane;
+        const int8_t *qb = reinterpret_cast<const int8_t *>(lds->sb[2 + pis]) + 64 - hjs + lane;
 #pragma unroll
         for (int q = 0; q < QR; q++) {
-            const int kappa = lane + 64 * q;
-            if (kappa < c) {
-                const int ip = hjs + 1 + kappa;
-                const uint32_t bp = (lds->par[pis][ip >> 5] >> (ip & 31)) & 1u;
-                const int32_t pv = (kappa < nps && kappa != kds) ? 1 - 2 * (int32_t)bp : 0;
-                int32_t qv = 0;
-                const int iq = hjs - 1 - kappa;
-                if (iq >= 0)
-                    qv = 1 - 2 * (int32_t)((lds->par[pis][iq >> 5] >> (iq & 31)) & 1u);
-                Cv[q] += -4 * sjs * (pv + qv);
-            }
+            const int32_t pv = (lane + 64 * q == kds) ? 0 : (int32_t)pb[64 * q];
+            Cv[q] = mad24_u(pv + (int32_t)qb[64 * q], f, Cv[q]);
         }
         lds_fence();
         // the flipped symbol and its mirror (m = 2c - js, half index nps) in the bit strings and
