@@ -664,6 +664,11 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
     // and are done by the outer loop, so the loop-carried walk state stays in scalar registers.
     bool need_restart = false;
     int32_t *trap_trp = nullptr; // trace record of a trap step, written once the restart is done
+    // The flip back to the state left by the last step leads to a visited state unless the insert
+    // of the current state overwrote that state's slot (slots are below 2^30): such a flip needs
+    // no probe.  jskip = that flip, or -1.
+    uint32_t slot_cur = (uint32_t)slot_of(w.h, w.x0, exact, tlog2);
+    int32_t jskip = -1;
     while (true) {
         if (need_restart) {
             need_restart = false;
@@ -672,8 +677,10 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
             start_bits(seed, walk_id, (uint32_t)restart_idx, n, w.x);
             clear_table(T, tlog2);
             w.rebuild();
+            slot_cur = (uint32_t)slot_of(w.h, w.x0, exact, tlog2);
+            jskip = -1;
             if (lane == 0)
-                T[slot_of(w.h, w.x0, exact, tlog2)] = w.h | 1ull;
+                T[slot_cur] = w.h | 1ull;
             if (trap_trp && lane == 0) {
                 trap_trp[0] = -1;
                 trap_trp[1] = w.isl;
@@ -692,7 +699,7 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
 #pragma unroll
             for (int g = 0; g < G; g++) {
                 const int j = w.flip(g);
-                keys[g] = (j < n) ? (((uint32_t)isl_j[g] << 8) | (uint32_t)j) : 0xFFFFFFFFu;
+                keys[g] = (j < n && j != jskip) ? (((uint32_t)isl_j[g] << 8) | (uint32_t)j) : 0xFFFFFFFFu;
                 if (scp && j < n)
                     scp[j] = isl_j[g];
             }
@@ -761,8 +768,13 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
                 break;
             }
             w.template commit<false>(js, isl_new);
-            if (w.lane == 0)
-                T[slot_of(w.h, w.x0, exact, tlog2)] = w.h | 1ull;
+            {
+                const uint32_t s_new = (uint32_t)slot_of(w.h, w.x0, exact, tlog2);
+                if (w.lane == 0)
+                    T[s_new] = w.h | 1ull;
+                jskip = s_new != slot_cur ? js : -1;
+                slot_cur = s_new;
+            }
             if (trp) {
                 if (w.lane == 0) {
                     trp[0] = js;
