@@ -389,20 +389,18 @@ struct MfmaWalker {
         // the flipped symbol and its mirror (m = 2c - js, half index nps) in the bit strings and
         // in the +-1 byte copies (kind p at byte a, kind 2+p at byte 63 - a when a <= 63; 0x01 and
         // 0xFF swap under xor 0xFE)
-        if (lane < 4 && ((lane & 1) == 0 || js != c)) {
-            const int a = (lane & 1) ? nps : hjs;
-            if (lane < 2) {
-                atomicXor(&lds->par[pis][a >> 5], 1u << (a & 31));
-                const int ar = kNA - 1 - a;
-                atomicXor(&lds->rev[pis][ar >> 5], 1u << (ar & 31));
-                atomicXor(&lds->sb[pis][a >> 2], 0xFEu << (8 * (a & 3)));
-                if (lane == 0) // the free bit itself
-                    atomicXor(&lds->xw[js >> 5], 1u << (js & 31));
-            } else {
-                const int u = 63 - a;
-                if (u >= 0)
-                    atomicXor(&lds->sb[2 + pis][u >> 2], 0xFEu << (8 * (u & 3)));
-            }
+        // (lane 0: js, lane 1: the mirror; toggles that do not apply xor 0, so there is one branch)
+        if (lane < (js != c ? 2 : 1)) {
+            const int a = lane ? nps : hjs;
+            atomicXor(&lds->par[pis][a >> 5], 1u << (a & 31));
+            const int ar = kNA - 1 - a;
+            atomicXor(&lds->rev[pis][ar >> 5], 1u << (ar & 31));
+            atomicXor(&lds->sb[pis][a >> 2], 0xFEu << (8 * (a & 3)));
+            const int u = 63 - a;
+            atomicXor(&lds->sb[2 + pis][max(u, 0) >> 2], u >= 0 ? 0xFEu << (8 * (u & 3)) : 0u);
+            // the free bit itself (lane 1 xors 0 into the next word: a lane-varying address keeps
+            // the compiler from turning the toggle into a cross-lane reduction)
+            atomicXor(&lds->xw[(js >> 5) + lane], lane == 0 ? 1u << (js & 31) : 0u);
         }
         lds_fence();
 #pragma unroll

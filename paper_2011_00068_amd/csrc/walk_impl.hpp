@@ -546,8 +546,10 @@ __device__ inline uint64_t slot_of(uint64_t hh, uint32_t x0, bool exact, int log
 // ---------------------------------------------------------------------------------------------
 // One walk, advanced until its budget, its target, or the launch's step limit.
 // ---------------------------------------------------------------------------------------------
-template <class W, int PW>
-__device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *__restrict__ tables,
+// TRACE = false: the walk records no trace and no scores, and the step loop carries no test for
+// them (run_walk below picks the instantiation).
+template <class W, int PW, bool TRACE>
+__device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint64_t *__restrict__ tables,
                          int32_t *__restrict__ trace, int32_t *__restrict__ scores, int64_t chunk,
                          typename W::Lds *lds, const uint64_t *zk)
 {
@@ -656,8 +658,8 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
     int32_t best_ts = -1, hit_ts = -1, watch_ts = -1;
     // steps left before the budget, as seen from this launch (periodic restarts stop there)
     const int32_t left32 = (int32_t)min<int64_t>(steps - t0, INT32_MAX);
-    int32_t *trp = trace_off >= 0 ? trace + 2 * (trace_off + t0) : nullptr;
-    int32_t *scp = score_off >= 0 ? scores + score_off + t0 * n : nullptr;
+    int32_t *trp = (TRACE && trace_off >= 0) ? trace + 2 * (trace_off + t0) : nullptr;
+    int32_t *scp = (TRACE && score_off >= 0) ? scores + score_off + t0 * n : nullptr;
     int32_t ts = 0;
 
     // The hot loop below only ever commits moves; restarts (a trap, or a periodic one) leave it
@@ -681,7 +683,7 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
             jskip = -1;
             if (lane == 0)
                 T[slot_cur] = w.h | 1ull;
-            if (trap_trp && lane == 0) {
+            if (TRACE && trap_trp && lane == 0) {
                 trap_trp[0] = -1;
                 trap_trp[1] = w.isl;
             }
@@ -700,7 +702,7 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
             for (int g = 0; g < G; g++) {
                 const int j = w.flip(g);
                 keys[g] = (j < n && j != jskip) ? (((uint32_t)isl_j[g] << 8) | (uint32_t)j) : 0xFFFFFFFFu;
-                if (scp && j < n)
+                if (TRACE && scp && j < n)
                     scp[j] = isl_j[g];
             }
 
@@ -760,9 +762,9 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
                 if (rem == 0)
                     rem = R32;
                 trap_trp = trp;
-                if (trp)
+                if (TRACE && trp)
                     trp += 2;
-                if (scp)
+                if (TRACE && scp)
                     scp += n;
                 need_restart = true;
                 break;
@@ -775,14 +777,14 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
                 jskip = s_new != slot_cur ? js : -1;
                 slot_cur = s_new;
             }
-            if (trp) {
+            if (TRACE && trp) {
                 if (w.lane == 0) {
                     trp[0] = js;
                     trp[1] = w.isl;
                 }
                 trp += 2;
             }
-            if (scp)
+            if (TRACE && scp)
                 scp += n;
             if (w.isl <= thr) {
                 if (w.isl < best32) {
@@ -844,6 +846,17 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
         ws.status = (t >= steps || (target >= 0 && hit >= 0)) ? kDone : kRunning;
     }
     (void)L;
+}
+
+template <class W, int PW>
+__device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *__restrict__ tables,
+                         int32_t *__restrict__ trace, int32_t *__restrict__ scores, int64_t chunk,
+                         typename W::Lds *lds, const uint64_t *zk)
+{
+    if (su(wsp->trace_offset) >= 0 || su(wsp->score_offset) >= 0)
+        run_walk_impl<W, PW, true>(wsp, tables, trace, scores, chunk, lds, zk);
+    else
+        run_walk_impl<W, PW, false>(wsp, tables, trace, scores, chunk, lds, zk);
 }
 
 // ---------------------------------------------------------------------------------------------
