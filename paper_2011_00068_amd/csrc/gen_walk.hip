@@ -34,6 +34,7 @@ struct WaveLdsGen {
     uint32_t fw[kGenWords]; // bit a = b_a: the free bits (words 0 .. kXWords-1), zero padded
     uint32_t rv[kGenWords];
     uint32_t bestx[kXWords]; // free bits of the best state of the walk so far
+    int32_t book[8];         // the walk loop's rarely updated bookkeeping
     int32_t C[kGenLMax + 1];   // C_k at index k, 0 past L-1
     int32_t psx[kGenLMax + 1]; // psx[a] = sum_{k=1..a} C_k
 };
@@ -58,6 +59,7 @@ struct GenWalker {
 
     __device__ __forceinline__ uint32_t *x_lds() const { return lds->fw; }
     __device__ __forceinline__ uint32_t *best_lds() const { return lds->bestx; }
+    __device__ __forceinline__ int32_t *book_lds() const { return lds->book; }
 
     // b_js (uniform) from the lane that scores flip js
     __device__ __forceinline__ uint32_t sbit_of(int js) const
@@ -274,8 +276,10 @@ struct GenWalker {
         if (REG_X)
             xflip_uniform(x, js);
         x0 ^= js < 32 ? 1u << js : 0u;
-        const uint64_t z = zk[js];
-        h ^= ((uint64_t)uniform((uint32_t)(z >> 32)) << 32) | uniform((uint32_t)z);
+        if (REG_X) { // else the caller sets h (it has the neighbour's hash from its probe)
+            const uint64_t z = zk[js];
+            h ^= ((uint64_t)uniform((uint32_t)(z >> 32)) << 32) | uniform((uint32_t)z);
+        }
         isl = isl_new;
     }
 };

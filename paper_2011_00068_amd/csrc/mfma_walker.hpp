@@ -56,6 +56,7 @@ struct WaveLdsMfma {
     uint32_t rev[2][kRevWords];     // bit a of rev[p] = bit (kNA-1-a) of par[p], 0 past kNA-1
     uint32_t xw[kXWords];           // free bits (kept current by every commit)
     uint32_t bestx[kXWords];        // free bits of the best state of the walk so far
+    int32_t book[8];                // the walk loop's rarely updated bookkeeping
     int32_t C[kMfmaCWords];         // C'_kappa at index kappa
     uint32_t sb[4][kMfmaSeqStride]; // +-1 byte copies of the A strings (first kMfmaSeqDwords used)
     uint32_t cb[4][kMfmaCDwords];   // C' as int8, four copies shifted by 0..3 bytes
@@ -103,14 +104,7 @@ struct MfmaWalker {
 
     __device__ __forceinline__ uint32_t *x_lds() const { return lds->xw; }
     __device__ __forceinline__ uint32_t *best_lds() const { return lds->bestx; }
-
-    // b_js (uniform) from the lane that scores flip js: mult > 0 iff s_js = -1
-    __device__ __forceinline__ uint32_t sbit_of(int js) const
-    {
-        const int32_t v0 = __builtin_amdgcn_readlane(mult[0], js >> 1);
-        const int32_t v1 = __builtin_amdgcn_readlane(mult[1], js >> 1);
-        return ((js & 1) ? v1 : v0) > 0 ? 1u : 0u;
-    }
+    __device__ __forceinline__ int32_t *book_lds() const { return lds->book; }
 
     __device__ __forceinline__ void set_length(int len)
     {
@@ -369,7 +363,10 @@ struct MfmaWalker {
     __device__ __forceinline__ void commit(int js, int32_t isl_new)
     {
         const int lane = this->lane;
-        const uint32_t bjs = REG_X ? xbit_uniform(x, js) : sbit_of(js);
+        // the sign of s_js from the owner lane's mult
+        const int32_t m0 = __builtin_amdgcn_readlane(mult[0], js >> 1);
+        const int32_t m1 = __builtin_amdgcn_readlane(mult[1], js >> 1);
+        const uint32_t bjs = ((js & 1) ? m1 : m0) > 0 ? 1u : 0u;
         const int hjs = js >> 1;
         const int pis = js & 1;
         const int nps = (js == c) ? 0 : c - ((js + 1) >> 1);
@@ -409,8 +406,10 @@ struct MfmaWalker {
         if (REG_X)
             xflip_uniform(x, js);
         x0 ^= js < 32 ? 1u << js : 0u;
-        const uint64_t z = zk[js];
-        h ^= ((uint64_t)uniform((uint32_t)(z >> 32)) << 32) | uniform((uint32_t)z);
+        if (REG_X) { // else the caller sets h (it has the neighbour's hash from its probe)
+            const uint64_t z = zk[js];
+            h ^= ((uint64_t)uniform((uint32_t)(z >> 32)) << 32) | uniform((uint32_t)z);
+        }
         isl = isl_new;
     }
 };

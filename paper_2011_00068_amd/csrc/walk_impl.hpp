@@ -46,6 +46,7 @@ struct WaveLdsBits {
     uint32_t rev[2][kRevWords]; // bit a of rev[p] = bit (kNA-1-a) of par[p], 0 past kNA-1
     uint32_t xw[kXWords];       // free bits (kept current by every commit)
     uint32_t bestx[kXWords];    // free bits of the best state of the walk so far
+    int32_t book[8];            // the walk loop's rarely updated bookkeeping
     int32_t C[kCMax + 1];       // C_{2 kappa + 2} at index kappa (0 for kappa >= c)
     int32_t psx[kCMax + 2];     // psx[a] = sum_{kappa < a} C
 };
@@ -151,6 +152,7 @@ struct Walker {
     // LDS copies of the current and of the best free bits
     __device__ __forceinline__ uint32_t *x_lds() const { return lds->xw; }
     __device__ __forceinline__ uint32_t *best_lds() const { return lds->bestx; }
+    __device__ __forceinline__ int32_t *book_lds() const { return lds->book; }
 
     // b_js (uniform) from the lane that scores flip js
     __device__ __forceinline__ uint32_t sbit_of(int js) const
@@ -462,7 +464,7 @@ struct Walker {
     }
 
     // Commit flip js (uniform): update C_k by dC_k, the bit strings / sequence, the free bits
-    // (lds->xw and x0; the register copy x as well when REG_X) and the hash.
+    // (lds->xw and x0; the register copy x and the hash as well when REG_X).
     template <bool REG_X = true>
     __device__ __forceinline__ void commit(int js, int32_t isl_new)
     {
@@ -515,8 +517,10 @@ struct Walker {
         if (REG_X)
             xflip_uniform(x, js);
         x0 ^= js < 32 ? 1u << js : 0u;
-        const uint64_t z = zk[js];
-        h ^= ((uint64_t)uniform((uint32_t)(z >> 32)) << 32) | uniform((uint32_t)z);
+        if (REG_X) { // else the caller sets h (it has the neighbour's hash from its probe)
+            const uint64_t z = zk[js];
+            h ^= ((uint64_t)uniform((uint32_t)(z >> 32)) << 32) | uniform((uint32_t)z);
+        }
         isl = isl_new;
     }
 };
@@ -638,24 +642,34 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
     const int32_t wch = watch < 0 ? -1 : (int32_t)min<int64_t>(watch, INT32_MAX);
     const int32_t R32 = (int32_t)min<int64_t>(R, INT32_MAX);
     int32_t rem = (R > 0) ? (int32_t)min<int64_t>((t0 / R + 1) * R - t0, INT32_MAX) : INT32_MAX;
-    bool hit_found = hit >= 0;
-    bool watch_found = wstep >= 0;
-    int32_t best32 = (int32_t)best_isl;
-    // the step loop runs while ts < lim; reaching the target sets lim = ts
-    int32_t lim = (tgt >= 0 && hit_found) ? 0 : nsteps;
-    // A committed state needs the bookkeeping below only if its ISL is at most thr: a new best,
-    // or the target or watch level not reached before.
-    auto threshold = [&]() -> int32_t {
-        int32_t v = best32 - 1;
-        if (tgt >= 0 && !hit_found)
+    const bool hit_found0 = hit >= 0;
+    const bool watch_found0 = wstep >= 0;
+    // The step loop runs while ts < lim; reaching the target sets lim = -1 (stopped).
+    int32_t lim = (tgt >= 0 && hit_found0) ? -1 : nsteps;
+    // A committed state needs bookkeeping only if its ISL is at most thr: a new best, or the target
+    // or watch level not reached before.  That bookkeeping (rarely updated) lives in LDS, so the
+    // step loop carries only thr and lim: book[0] best ISL, [1] its step in this launch, [2] / [3]
+    // the steps that reached the target / watch level (-1: not in this launch), [4] / [5] whether
+    // they have been reached.
+    auto threshold = [&](int32_t best, bool hf, bool wf) -> int32_t {
+        int32_t v = best - 1;
+        if (tgt >= 0 && !hf)
             v = max(v, tgt);
-        if (wch >= 0 && !watch_found)
+        if (wch >= 0 && !wf)
             v = max(v, wch);
         return v;
     };
-    int32_t thr = threshold();
+    int32_t thr = threshold((int32_t)best_isl, hit_found0, watch_found0);
+    int32_t *const bk = w.book_lds();
+    if (lane == 0) {
+        bk[0] = (int32_t)best_isl;
+        bk[1] = -1;
+        bk[2] = -1;
+        bk[3] = -1;
+        bk[4] = hit_found0;
+        bk[5] = watch_found0;
+    }
     // steps of this launch at which best / hit / watch were reached (-1 = not in this launch)
-    int32_t best_ts = -1, hit_ts = -1, watch_ts = -1;
     // steps left before the budget, as seen from this launch (periodic restarts stop there)
     const int32_t left32 = (int32_t)min<int64_t>(steps - t0, INT32_MAX);
     int32_t *trp = (TRACE && trace_off >= 0) ? trace + 2 * (trace_off + t0) : nullptr;
@@ -709,6 +723,7 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
             // best non-visited flip: take the PW smallest keys, probe them together
             int js = -1;
             int32_t isl_new = 0;
+            uint64_t h_new = 0; // hash of the chosen neighbour (from its probe)
             while (true) {
                 uint32_t cand[PW];
 #pragma unroll
@@ -747,6 +762,8 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
                         pick = (first == i) ? cand[i] : pick;
                     js = (int)(pick & 255u);
                     isl_new = (int32_t)(pick >> 8);
+                    h_new = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(hc >> 32), first) << 32) |
+                            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)hc, first);
                     break;
                 }
                 if (cand[PW - 1] == 0xFFFFFFFFu)
@@ -770,6 +787,7 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
                 break;
             }
             w.template commit<false>(js, isl_new);
+            w.h = h_new;
             {
                 const uint32_t s_new = (uint32_t)slot_of(w.h, w.x0, exact, tlog2);
                 if (w.lane == 0)
@@ -787,27 +805,36 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
             if (TRACE && scp)
                 scp += n;
             if (w.isl <= thr) {
-                if (w.isl < best32) {
-                    best32 = w.isl;
-                    best_ts = ts;
-                    if (w.lane < kXWords)
-                        bl[w.lane] = xl[w.lane];
+                // uniform updates first, then one lane-0 store block (so that thr and lim stay
+                // scalar)
+                int32_t best = su(bk[0]);
+                int32_t hf = su(bk[4]), wf = su(bk[5]);
+                const bool nb = w.isl < best;
+                const bool nh = tgt >= 0 && !hf && w.isl <= tgt;
+                const bool nw = wch >= 0 && !wf && w.isl <= wch;
+                best = nb ? w.isl : best;
+                hf |= nh ? 1 : 0;
+                wf |= nw ? 1 : 0;
+                lim = nh ? -1 : lim;
+                thr = su(threshold(best, hf != 0, wf != 0));
+                if (nb && w.lane < kXWords)
+                    bl[w.lane] = xl[w.lane];
+                if (w.lane == 0) {
+                    bk[0] = best;
+                    if (nb)
+                        bk[1] = ts;
+                    if (nh)
+                        bk[2] = ts;
+                    if (nw)
+                        bk[3] = ts;
+                    bk[4] = hf;
+                    bk[5] = wf;
                 }
-                if (tgt >= 0 && !hit_found && w.isl <= tgt) {
-                    hit_found = true;
-                    hit_ts = ts;
-                    lim = ts;
-                }
-                if (wch >= 0 && !watch_found && w.isl <= wch) {
-                    watch_found = true;
-                    watch_ts = ts;
-                }
-                thr = threshold();
             }
             if (rem == 0) {
                 rem = R32;
                 // periodic restart (not after the last step, not once stopped)
-                if (ts < left32 && !(tgt >= 0 && hit_found)) {
+                if (ts < left32 && lim >= 0) {
                     need_restart = true;
                     break;
                 }
@@ -818,7 +845,9 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
     }
     t = t0 + ts;
     flips = flips0 + (int64_t)ts * n;
-    best_isl = best32;
+    lds_fence();
+    const int32_t best_ts = su(bk[1]), hit_ts = su(bk[2]), watch_ts = su(bk[3]);
+    best_isl = su(bk[0]);
     if (best_ts >= 0)
         best_step = t0 + best_ts;
     if (hit_ts >= 0)
