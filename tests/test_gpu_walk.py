@@ -118,6 +118,32 @@ def test_restarts_traps_targets(labs):
     assert res[0]["traps"] >= 1
 
 
+def test_restarts_traps_targets_untraced(labs):
+    # the same cases without traces or scores run the step loop built without trace tests; a
+    # batch mixing traced and untraced walks runs both forms side by side
+    cfgs = [
+        labs.make_cfg(5, SEED, 0, steps=60, table_log2=8),
+        labs.make_cfg(7, SEED, 1, steps=200, table_log2=3),
+        labs.make_cfg(51, SEED, 7, steps=205, restart_period=40),
+        labs.make_cfg(101, SEED, 9, steps=500, target_isl=1500),
+        labs.make_cfg(101, SEED, 9, steps=500, watch_isl=1500),
+        labs.make_cfg(101, SEED, 9, steps=500, target_isl=1500, watch_isl=1700, restart_period=97),
+        labs.make_cfg(255, SEED, 3, steps=300, restart_period=64, table_log2=10),
+        labs.make_cfg(255, SEED, 3, steps=300, restart_period=64, table_log2=10, trace=True),
+        labs.make_cfg(201, SEED, 5, steps=400, restart_period=150, watch_isl=3000),
+    ]
+    for variant in (1, 2, 3):
+        for opt in (dict(), dict(steps_per_launch=61)):
+            plan = labs.WalkPlan(cfgs, variant=variant, **opt)
+            plan.run()
+            res = plan.results()
+            plan.close()
+            for i, c in enumerate(cfgs):
+                r = oracle_walk(c, trace=bool(c.flags & 1), score_trace=bool(c.flags & 2))
+                assert_same(res[i], r, (i, variant, opt))
+    assert res[0]["traps"] >= 1
+
+
 def test_target_met_by_start_state(labs):
     start_isl = o.isl(o.skew_expand(101, o.start_bits(101, SEED, 4, 0)))
     c = labs.make_cfg(101, SEED, 4, steps=100, target_isl=start_isl)
