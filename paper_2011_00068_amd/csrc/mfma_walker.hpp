@@ -395,9 +395,9 @@ struct MfmaWalker {
             atomicXor(&lds->sb[pis][a >> 2], 0xFEu << (8 * (a & 3)));
             const int u = 63 - a;
             atomicXor(&lds->sb[2 + pis][max(u, 0) >> 2], u >= 0 ? 0xFEu << (8 * (u & 3)) : 0u);
-            // the free bit itself (lane 1 xors 0 into the next word: a lane-varying address keeps
+            // the free bit itself (lane 1 xors 0 into a neighbouring word: a lane-varying address keeps
             // the compiler from turning the toggle into a cross-lane reduction)
-            atomicXor(&lds->xw[(js >> 5) + lane], lane == 0 ? 1u << (js & 31) : 0u);
+            atomicXor(&lds->xw[(js >> 5) ^ lane], lane == 0 ? 1u << (js & 31) : 0u);
         }
         lds_fence();
 #pragma unroll

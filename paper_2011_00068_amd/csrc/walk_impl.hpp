@@ -38,7 +38,7 @@ namespace liblabs {
 // ---------------------------------------------------------------------------------------------
 // Per-wave LDS block.
 // ---------------------------------------------------------------------------------------------
-constexpr int kSeqOff = 384;   // direct variant: s_i stored at s8[kSeqOff + i]
+constexpr int kSeqOff = 384;   // s_i stored at s8[kSeqOff + i]
 constexpr int kSeqBytes = 1280; // zero padding on both sides covers every j +- k
 
 struct WaveLdsBits {
@@ -49,14 +49,13 @@ struct WaveLdsBits {
     int32_t book[8];            // the walk loop's rarely updated bookkeeping
     int32_t C[kCMax + 1];       // C_{2 kappa + 2} at index kappa (0 for kappa >= c)
     int32_t psx[kCMax + 2];     // psx[a] = sum_{kappa < a} C
+    int8_t s8[kSeqBytes];       // s_i at kSeqOff + i, 0 elsewhere
 };
 
-struct WaveLdsDirect : WaveLdsBits {
-    int8_t s8[kSeqBytes]; // s_i at kSeqOff + i, 0 elsewhere
-};
-
+// both variants keep the same block (the direct one scores from s8, the bit-sliced one commits
+// from it)
+using WaveLdsDirect = WaveLdsBits;
 template <bool DIRECT> struct LdsOf { using type = WaveLdsBits; };
-template <> struct LdsOf<true> { using type = WaveLdsDirect; };
 
 __device__ inline void lds_fence() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront"); __builtin_amdgcn_wave_barrier(); }
 
@@ -108,11 +107,10 @@ struct FlipConst {
     const uint32_t *wq; // rev[j&1] word holding bit kNA-hj (start of the q window)
     uint32_t sp;        // p-window shift hj+1; the q-window shift kNA-hj = 1 - sp (mod 32)
     const int32_t *psx_np, *psx_nq; // PSX at the counts of valid p / q shifts
-    const int32_t *c_kd;            // C at the excluded shift d = L-1-2j
-    const uint32_t *qd_word;        // par word holding b_{j-d} (j - d >= 0 iff 3 j >= 2 c)
-    uint32_t qd_shift;              // its bit
-    uint32_t m_par;                 // (c - j) & 1: s_m = (-1)^(c-j) s_j
-    int32_t hconst;                 // np + 3 nq - 1 (H_j without the data-dependent terms)
+    const int32_t *c_kd;            // C at the excluded shift d = L-1-2j (a zero word for the centre)
+    const int8_t *qd;               // s_{j-d} (a zero byte where j - d < 0 and for the centre)
+    int32_t hc;                     // np + 3 nq - 1 (H_j without the data-dependent terms); nq
+                                    // for the centre
     int32_t nq;                     // valid q shifts: floor(j/2)
 };
 
@@ -133,7 +131,8 @@ struct Walker {
     uint32_t x[kXWords]; // free bits; current only where commit<true> is used (else in lds->xw)
     uint32_t x0;         // free bits 0..31, always current (they address the exact table)
     int32_t Cv[QR];
-    int32_t sbit[G];
+    int32_t mult[G];  // factor of T_j (see score()): -8 s_j, -4 s_c for the centre, 0 past it
+    int32_t eps8;     // 8 (-1)^(c-j) for this lane's flips (the parity of j - lane is even)
     int planes;
     Lds *lds;
     const uint64_t *zk;
@@ -154,18 +153,19 @@ struct Walker {
     __device__ __forceinline__ uint32_t *best_lds() const { return lds->bestx; }
     __device__ __forceinline__ int32_t *book_lds() const { return lds->book; }
 
-    // b_js (uniform) from the lane that scores flip js
+    // b_js (uniform) from the lane that scores flip js: mult > 0 iff s_js = -1
     __device__ __forceinline__ uint32_t sbit_of(int js) const
     {
-        uint32_t v = 0;
+        int32_t v = 0;
 #pragma unroll
         for (int g = 0; g < G; g++)
-            v = (g == (js >> 6)) ? (uint32_t)__builtin_amdgcn_readlane(sbit[g], js & 63) : v;
-        return v;
+            v = (g == (js >> 6)) ? __builtin_amdgcn_readlane(mult[g], js & 63) : v;
+        return v > 0 ? 1u : 0u;
     }
 
     __device__ __forceinline__ void init_lanes(int ln)
     {
+        eps8 = ((c - ln) & 1) ? -8 : 8;
         if constexpr (!DIRECT)
             setup_lanes(ln);
     }
@@ -185,14 +185,16 @@ struct Walker {
             f.wq = &lds->rev[p][(kNA - hj) >> 5];
             f.psx_np = &lds->psx[np];
             f.psx_nq = &lds->psx[nq];
-            f.c_kd = &lds->C[max(c - 1 - j, 0)];
-            const int iq = 3 * j - 2 * c;
-            const int a = max(iq, 0) >> 1;
-            f.qd_word = &lds->par[p][a >> 5];
-            f.qd_shift = (uint32_t)(a & 31);
-            f.m_par = (uint32_t)((c - j) & 1);
-            f.hconst = np + 3 * nq - 1;
             f.nq = nq;
+            if (j < c) {
+                f.c_kd = &lds->C[c - 1 - j];
+                f.qd = &lds->s8[kSeqOff + 3 * j - 2 * c]; // s_{j-d}, j - d = 3j - 2c >= -2c
+                f.hc = np + 3 * nq - 1;
+            } else { // the centre (and the unused slots past it)
+                f.c_kd = &lds->C[c];
+                f.qd = &lds->s8[0];
+                f.hc = nq;
+            }
         }
     }
 
@@ -241,18 +243,22 @@ struct Walker {
         if (lane < 2 * (kRevWords - 6)) {
             lds->rev[lane & 1][6 + (lane >> 1)] = 0u;
         }
-        if constexpr (DIRECT) {
-            for (int i = lane; i < kSeqBytes; i += kWave) {
-                const int pos = i - kSeqOff;
-                lds->s8[i] = (pos >= 0 && pos < L) ? (int8_t)(1 - 2 * (int)seq_bit(pos)) : (int8_t)0;
-            }
+        for (int i = lane; i < kSeqBytes; i += kWave) {
+            const int pos = i - kSeqOff;
+            lds->s8[i] = (pos >= 0 && pos < L) ? (int8_t)(1 - 2 * (int)seq_bit(pos)) : (int8_t)0;
         }
+        // prepare() writes C_kappa for kappa < 64 QR; the zero word C_c may lie past that
+        for (int i = lane; i < kCMax + 1; i += kWave)
+            lds->C[i] = 0;
         lds_fence();
         // per-lane free bits of the owned flips
+        int32_t sbit[G];
 #pragma unroll
         for (int g = 0; g < G; g++) {
             const int j = lane + 64 * g;
             sbit[g] = (j <= c) ? (int32_t)seq_bit(j) : 0;
+            const int32_t sj = 1 - 2 * sbit[g];
+            mult[g] = j < c ? -8 * sj : (j == c ? -4 * sj : 0);
         }
         // C_k for even k from the parity strings: pairs (i, i+k) share the parity of i, and
         // s_i s_{i+k} = 1 - 2 (b_i xor b_{i+k}).
@@ -403,9 +409,13 @@ struct Walker {
                     acc[g] = (acc[g] << 2) + r * (int32_t)sw;
                 }
             }
-            // assemble ISL_j (products with +-1 are conditional negations).  For the centre, Wp
-            // equals Wq (Eq. (4) mirrors every even offset onto itself), so acc = 2 sum C Wq and
-            // G_c = PSX[nq] - acc, H_c = nq.
+            // assemble ISL_j.  With T_j = PSX[np] + PSX[nq] - 2 acc = sum_k C_k (p_k + q_k) and
+            // s_m = (-1)^(c-j) s_j:
+            //   ISL_j = ISL - 8 s_j (T_j - s_m C_d) + 16 (hc - 4 rc - 2 s_m q_d)
+            //         = ISL + 16 hc - 64 rc + 8 (-1)^(c-j) C_d - 8 s_j (T_j + 4 (-1)^(c-j) q_d).
+            // For the centre, Wp equals Wq (Eq. (4) mirrors every even offset onto itself), so rc = 0,
+            // T_c = 2 G_c, and with hc = nq, C_d = q_d = 0 and the factor -4 s_c the same
+            // expression gives ISL - 8 s_c G_c + 16 nq: every flip is assembled without branches.
 #pragma unroll
             for (int g = 0; g < G; g++) {
                 const FlipConst &f = fc[g];
@@ -417,21 +427,10 @@ struct Walker {
                 // nq lies in [32 g, 32 g + 31]: the low (nq - 32 g) bits of word g are both-sided
                 const uint32_t rmask = (1u << (f.nq & 31)) - 1u;
                 rc = bcnt_acc(((g < KW - g ? wp[g][g] : 0u) ^ wq[g][g]) & rmask, rc);
-                const int32_t Cd = *f.c_kd;
-                const int32_t pnp = *f.psx_np, pnq = *f.psx_nq;
-                const uint32_t qbit = (*f.qd_word >> f.qd_shift) & 1u;
-                const uint32_t m_neg = (uint32_t)sbit[g] ^ f.m_par; // s_m = -1
-                // s_m q_d in {-1, 0, +1}
-                const int j = this->lane + 64 * g;
-                const bool centre = j == c;
-                const bool qd_valid = 3 * j >= 2 * c; // j - d >= 0
-                const int32_t smqd = qd_valid ? ((m_neg ^ qbit) ? -1 : 1) : 0;
-                const int32_t Gg = pnp + pnq - 2 * acc[g] - (m_neg ? -Cd : Cd);
-                const int32_t Hg = f.hconst - 4 * (int32_t)rc - 2 * smqd; // np + nq + 2 R_j - 1 - 2 s_m q_d
-                const int32_t Gj = centre ? pnq - acc[g] : Gg;
-                const int32_t Hj = centre ? f.nq : Hg;
-                // ISL - 8 s_j G_j + 16 H_j
-                isl_j[g] = isl + (sbit[g] ? 8 * Gj : -8 * Gj) + 16 * Hj;
+                const int32_t T = *f.psx_np + *f.psx_nq - 2 * acc[g];
+                // |C_d| <= L, |T| <= L^2 / 2, factors within 8: 24-bit products
+                const int32_t base = isl + 16 * f.hc - 64 * (int32_t)rc + __mul24(eps8, *f.c_kd);
+                isl_j[g] = mad24(mult[g], mad24((int32_t)*f.qd, eps8 >> 1, T), base);
             }
         } else {
             // direct sum of squares over the even shifts
@@ -440,7 +439,7 @@ struct Walker {
             for (int g = 0; g < G; g++) {
                 const int j = lane + 64 * g;
                 const int jc = min(j, c);
-                const int32_t sj4 = 4 * (1 - 2 * sbit[g]);
+                const int32_t sj4 = 4 * (int32_t)s8[kSeqOff + jc];
                 const int pbase = (jc == c) ? kSeqOff + L : kSeqOff + jc; // centre: p_k = 0
                 const int qbase = kSeqOff + jc;
                 int32_t acc = 0;
@@ -469,51 +468,41 @@ struct Walker {
     __device__ __forceinline__ void commit(int js, int32_t isl_new)
     {
         const int lane = this->lane;
-        const int32_t sjs = 1 - 2 * (int32_t)(REG_X ? xbit_uniform(x, js) : sbit_of(js));
+        const uint32_t bjs = REG_X ? xbit_uniform(x, js) : sbit_of(js);
         const int hjs = js >> 1;
         const int pis = js & 1;
         const int nps = (js == c) ? 0 : c - ((js + 1) >> 1);
         const int kds = (js == c) ? -1 : c - 1 - js;
+        // dC_k = -4 s_js (p_k + q_k) with p_k = s_{js+k}, q_k = s_{js-k} read from the zero-padded
+        // sequence bytes (so lanes with kappa >= c add nothing), p without the excluded shift d;
+        // at the centre p = q and u = q, so the factor is halved instead
+        const int32_t fct = (js == c) ? (bjs ? 2 : -2) : (bjs ? 4 : -4);
+        const int8_t *pb = lds->s8 + kSeqOff + js + 2 + 2 * lane;
+        const int8_t *qb = lds->s8 + kSeqOff + js - 2 - 2 * lane;
 #pragma unroll
         for (int q = 0; q < QR; q++) {
-            const int kappa = lane + 64 * q;
-            if (kappa < c) {
-                int32_t pv = 0, qv = 0;
-                if constexpr (!DIRECT) {
-                    const int ip = hjs + 1 + kappa;
-                    const uint32_t bp = (lds->par[pis][ip >> 5] >> (ip & 31)) & 1u;
-                    pv = (kappa < nps && kappa != kds) ? 1 - 2 * (int32_t)bp : 0;
-                    const int iq = hjs - 1 - kappa;
-                    if (iq >= 0)
-                        qv = 1 - 2 * (int32_t)((lds->par[pis][iq >> 5] >> (iq & 31)) & 1u);
-                } else {
-                    const int k = 2 * kappa + 2;
-                    pv = (js == c || kappa == kds) ? 0 : (int32_t)lds->s8[kSeqOff + js + k];
-                    qv = (int32_t)lds->s8[kSeqOff + js - k];
-                }
-                Cv[q] += -4 * sjs * (pv + qv);
-            }
+            const int32_t pv = (lane + 64 * q == kds) ? 0 : (int32_t)pb[128 * q];
+            Cv[q] = mad24_u(pv + (int32_t)qb[-128 * q], fct, Cv[q]);
         }
         lds_fence();
-        if (lane == 2)
-            atomicXor(&lds->xw[js >> 5], 1u << (js & 31));
-        if constexpr (!DIRECT) {
-            if (lane < 2 && (lane == 0 || js != c)) {
-                const int a = (lane == 0) ? hjs : nps; // mirror m = 2c - js has a = nps
+        // lane 0: js, lane 1: the mirror m = 2c - js (half index nps); the free bit itself from
+        // lane 0 (lane 1 xors 0 into a neighbouring word: a lane-varying address keeps the compiler from
+        // turning the toggle into a cross-lane reduction)
+        if (lane < (js != c ? 2 : 1)) {
+            const int pos = lane ? 2 * c - js : js;
+            lds->s8[kSeqOff + pos] = (int8_t)(-lds->s8[kSeqOff + pos]);
+            if constexpr (!DIRECT) {
+                const int a = lane ? nps : hjs;
                 atomicXor(&lds->par[pis][a >> 5], 1u << (a & 31));
                 const int ar = kNA - 1 - a;
                 atomicXor(&lds->rev[pis][ar >> 5], 1u << (ar & 31));
             }
-        } else {
-            if (lane < 2 && (lane == 0 || js != c)) {
-                const int pos = (lane == 0) ? js : 2 * c - js;
-                lds->s8[kSeqOff + pos] = (int8_t)(-lds->s8[kSeqOff + pos]);
-            }
+            atomicXor(&lds->xw[(js >> 5) ^ lane], lane == 0 ? 1u << (js & 31) : 0u);
         }
         lds_fence();
 #pragma unroll
         for (int g = 0; g < G; g++)
-            sbit[g] ^= (lane + 64 * g == js) ? 1 : 0;
+            mult[g] = (lane + 64 * g == js) ? -mult[g] : mult[g];
         if (REG_X)
             xflip_uniform(x, js);
         x0 ^= js < 32 ? 1u << js : 0u;
@@ -1019,8 +1008,7 @@ __global__ void __launch_bounds__(64) k_flip_scores(int L, int count, const uint
     w.n = w.c + 1;
     w.lds = &lds;
     w.zk = zk;
-    if constexpr (!DIRECT)
-        w.setup_lanes(w.lane);
+    w.init_lanes(w.lane);
 #pragma unroll
     for (int i = 0; i < kXWords; i++)
         w.x[i] = xs[(int64_t)r * kXWords + i];
