@@ -869,8 +869,8 @@ static int resolve_opts(labs_walk_plan *p, const labs_plan_opts *in)
         o.waves_per_block = have ? tuned.waves_per_block : (o.variant == LABS_VARIANT_MFMA ? 2 : 1);
     if (o.waves_per_block != 1 && o.waves_per_block != 2 && o.waves_per_block != 4 && o.waves_per_block != 8)
         return fail(LABS_EINVAL, "waves_per_block = %d must be 0, 1, 2, 4 or 8", o.waves_per_block);
-    if (o.probe_width == 0)
-        o.probe_width = have ? tuned.probe_width : 2;
+    if (o.probe_width == 0) // measured: two probes in flight pay off for the matrix-core walker only
+        o.probe_width = have ? tuned.probe_width : (o.variant == LABS_VARIANT_MFMA ? 2 : 1);
     if (o.probe_width < 1 || o.probe_width > 4)
         return fail(LABS_EINVAL, "probe_width = %d must be in [0, 4]", o.probe_width);
     if (o.probe_width > 2)

@@ -271,12 +271,12 @@ struct MfmaWalker {
     __device__ __forceinline__ void prepare()
     {
         const int lane = this->lane;
-        bool wide = false; // some |C_k| above the int8 range
 #pragma unroll
-        for (int q = 0; q < QR; q++) {
+        for (int q = 0; q < QR; q++)
             lds->C[lane + 64 * q] = Cv[q];
-            wide = wide || (uint32_t)(Cv[q] + 128) > 255u;
-        }
+        // some |C'_kappa| above the int8 range?  |C'_kappa| <= L - 2 - 2 kappa <= 127 from kappa = 63
+        // on, so only the first 64 shifts need the test
+        const bool wide = (uint32_t)(Cv[0] + 128) > 255u;
         planes = ballot(wide) != 0ull ? 9 : 8; // only "fits int8 or not" is used
         put_c(0);
         if (planes > 8)
@@ -342,7 +342,7 @@ struct MfmaWalker {
                 uint32_t rc = bcnt_acc((wp0 ^ wq0) & f.m0, 0u);
                 rc = bcnt_acc((wp1 ^ wq1) & f.m1, rc);
                 // |C'| <= 253: a 24-bit product
-                base[g] = isl + 16 * f.hc - 64 * (int32_t)rc + __mul24(eps8[g], *f.c_kd);
+                base[g] = mad24((int32_t)rc, -64, isl + 16 * f.hc) + __mul24(eps8[g], *f.c_kd);
             }
         }
         mfma_v4i d = tile();
@@ -400,9 +400,9 @@ struct MfmaWalker {
             atomicXor(&lds->xw[(js >> 5) ^ lane], lane == 0 ? 1u << (js & 31) : 0u);
         }
         lds_fence();
-#pragma unroll
-        for (int g = 0; g < G; g++)
-            mult[g] = (2 * lane + g == js) ? -mult[g] : mult[g];
+        const bool own = lane == (js >> 1); // this lane scores js
+        mult[0] = (own && !(js & 1)) ? -mult[0] : mult[0];
+        mult[1] = (own && (js & 1)) ? -mult[1] : mult[1];
         if (REG_X)
             xflip_uniform(x, js);
         x0 ^= js < 32 ? 1u << js : 0u;

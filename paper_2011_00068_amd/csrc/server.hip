@@ -128,7 +128,7 @@ void scheduler(labs_server *S)
     WalkLaunch lp{};
     lp.variant = LABS_VARIANT_BITSLICE;
     lp.waves_per_block = 1;
-    lp.probe_width = 2;
+    lp.probe_width = 1; // the bit-sliced walker's faster setting (measured)
     lp.shape = -1;
     lp.chunk = S->opts.steps_per_tick;
     lp.persistent = 0;
