@@ -29,6 +29,8 @@ namespace {
 constexpr int kGenLMax = kXWords * 32; // 192
 constexpr int kGenWords = 16;          // bit-string words, zero padded past the sequence
 constexpr int kGenRV = kGenLMax - 1;   // reversed string: bit a = b_{kGenRV - a}
+constexpr int kGenSeqOff = kGenLMax;   // s_i at s8[kGenSeqOff + i]; zero padding covers every j +- k
+constexpr int kGenSeqBytes = 3 * kGenLMax;
 
 struct WaveLdsGen {
     uint32_t fw[kGenWords]; // bit a = b_a: the free bits (words 0 .. kXWords-1), zero padded
@@ -37,6 +39,7 @@ struct WaveLdsGen {
     int32_t book[8];         // the walk loop's rarely updated bookkeeping
     int32_t C[kGenLMax + 1];   // C_k at index k, 0 past L-1
     int32_t psx[kGenLMax + 1]; // psx[a] = sum_{k=1..a} C_k
+    int8_t s8[kGenSeqBytes];   // s_i at kGenSeqOff + i, 0 elsewhere
 };
 
 template <int G, int KW>
@@ -52,7 +55,7 @@ struct GenWalker {
     uint32_t x[kXWords]; // free bits; current only where commit<true> is used (else in lds->fw)
     uint32_t x0;         // free bits 0..31, always current
     int32_t Cv[QR];
-    int32_t sbit[G];
+    int32_t mult[G]; // -4 s_j (0 past the last flip)
     int planes;
     Lds *lds;
     const uint64_t *zk;
@@ -61,14 +64,14 @@ struct GenWalker {
     __device__ __forceinline__ uint32_t *best_lds() const { return lds->bestx; }
     __device__ __forceinline__ int32_t *book_lds() const { return lds->book; }
 
-    // b_js (uniform) from the lane that scores flip js
+    // b_js (uniform) from the lane that scores flip js: mult > 0 iff s_js = -1
     __device__ __forceinline__ uint32_t sbit_of(int js) const
     {
-        uint32_t v = 0;
+        int32_t v = 0;
 #pragma unroll
         for (int g = 0; g < G; g++)
-            v = (g == (js >> 6)) ? (uint32_t)__builtin_amdgcn_readlane(sbit[g], js & 63) : v;
-        return v;
+            v = (g == (js >> 6)) ? __builtin_amdgcn_readlane(mult[g], js & 63) : v;
+        return v > 0 ? 1u : 0u;
     }
 
     __device__ __forceinline__ void set_length(int len)
@@ -105,10 +108,16 @@ struct GenWalker {
             lds->rv[lane] = r;
         }
         lds_fence();
+        for (int i = lane; i < kGenSeqBytes; i += kWave) {
+            const int pos = i - kGenSeqOff;
+            lds->s8[i] = (pos >= 0 && pos < L) ? (int8_t)(1 - 2 * (int)bit(pos)) : (int8_t)0;
+        }
+        int32_t sbit[G];
 #pragma unroll
         for (int g = 0; g < G; g++) {
             const int j = lane + 64 * g;
             sbit[g] = (j < n) ? (int32_t)bit(j) : 0;
+            mult[g] = j < n ? 8 * sbit[g] - 4 : 0;
         }
         int32_t sq = 0;
 #pragma unroll
@@ -240,10 +249,9 @@ struct GenWalker {
 #pragma unroll
             for (int w = 0; w < RW; w++)
                 rc = bcnt_acc((wp[g][w] ^ wq[g][w]) & low_mask(m - 32 * w), rc);
-            const int32_t Rj = m - 2 * (int32_t)rc;
+            // ISL - 4 s_j G_j + 4 H_j with H_j = (L-1) + 2 (m - 2 rc); |G_j| <= L^2: 24-bit products
             const int32_t Gj = lds->psx[np] + lds->psx[nq] - 2 * acc[g];
-            const int32_t Hj = (L - 1) + 2 * Rj;
-            isl_j[g] = isl + (sbit[g] ? 4 * Gj : -4 * Gj) + 4 * Hj;
+            isl_j[g] = mad24(mult[g], Gj, mad24((int32_t)rc, -16, isl + 4 * (L - 1) + 8 * m));
         }
     }
 
@@ -252,19 +260,20 @@ struct GenWalker {
     __device__ __forceinline__ void commit(int js, int32_t isl_new)
     {
         const int lane = this->lane;
-        const int32_t sjs = 1 - 2 * (int32_t)(REG_X ? xbit_uniform(x, js) : sbit_of(js));
+        const uint32_t bjs = REG_X ? xbit_uniform(x, js) : sbit_of(js);
+        // dC_k = -2 s_js (s_{js+k} + s_{js-k}), read from the zero-padded sequence bytes (so
+        // shifts past either end add nothing)
+        const int32_t fct = bjs ? 2 : -2;
+        const int8_t *pb = lds->s8 + kGenSeqOff + js + 1 + lane;
+        const int8_t *qb = lds->s8 + kGenSeqOff + js - 1 - lane;
 #pragma unroll
-        for (int q = 0; q < QR; q++) {
-            const int k = lane + 64 * q + 1;
-            if (k < L) {
-                const int32_t pv = (js + k < L) ? 1 - 2 * (int32_t)bit(js + k) : 0;
-                const int32_t qv = (js - k >= 0) ? 1 - 2 * (int32_t)bit(js - k) : 0;
-                Cv[q] += -2 * sjs * (pv + qv);
-            }
-        }
+        for (int q = 0; q < QR; q++)
+            Cv[q] = mad24_u((int32_t)pb[64 * q] + (int32_t)qb[-64 * q], fct, Cv[q]);
         lds_fence();
-        if (lane == 0)
+        if (lane == 0) {
             lds->fw[js >> 5] ^= 1u << (js & 31);
+            lds->s8[kGenSeqOff + js] = (int8_t)(-lds->s8[kGenSeqOff + js]);
+        }
         if (lane == 1) {
             const int a = kGenRV - js;
             lds->rv[a >> 5] ^= 1u << (a & 31);
@@ -272,7 +281,7 @@ struct GenWalker {
         lds_fence();
 #pragma unroll
         for (int g = 0; g < G; g++)
-            sbit[g] ^= (lane + 64 * g == js) ? 1 : 0;
+            mult[g] = (lane + 64 * g == js) ? -mult[g] : mult[g];
         if (REG_X)
             xflip_uniform(x, js);
         x0 ^= js < 32 ? 1u << js : 0u;
