@@ -28,6 +28,8 @@
 //    H = nq.
 //  * DIRECT: the sequence as int8 in LDS (zero padded), C as int32 in LDS, and the sum of
 //    (C_k - 4 s_j u_jk)^2 accumulated term by term, with the k = d term fixed up afterwards.
+// Both keep that zero-padded int8 copy of the sequence: the commit reads p_k and q_k from it
+// (so shifts past either end need no test), and the bit-sliced assembly reads q_d from it.
 
 #pragma once
 
