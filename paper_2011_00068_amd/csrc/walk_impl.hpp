@@ -951,7 +951,7 @@ constexpr int kMaxWavesPerBlock = 8;
 
 // Occupancy target of the walk kernel per shape: the smaller shapes fit 8 waves per SIMD (64
 // VGPRs), the 3-group shapes keep more windows in registers.
-template <int SHAPE> struct WavesPerEu { static constexpr int value = (SHAPE >= 0 && SHAPE <= 4) ? 8 : 4; };
+template <int SHAPE> struct WavesPerEu { static constexpr int value = (SHAPE >= 0 && SHAPE <= 4) ? 8 : 6; };
 
 template <int SHAPE, bool DIRECT, int PW>
 __global__ void __launch_bounds__(64 * kMaxWavesPerBlock)
