@@ -174,11 +174,11 @@ typedef struct labs_walk_result {
 
 /* Kernel variants: results never depend on the choice. */
 #define LABS_VARIANT_AUTO 0     /* autotuned (labs_autotune cache), else LABS_VARIANT_MFMA when
-                                   every walk has 129 <= L <= 255, else LABS_VARIANT_BITSLICE */
+                                   every walk has L >= 129, else LABS_VARIANT_BITSLICE */
 #define LABS_VARIANT_BITSLICE 1 /* bit-sliced correlation table, popcount scoring */
 #define LABS_VARIANT_DIRECT 2   /* int8 sequence + int32 table in LDS, direct sum of squares */
-#define LABS_VARIANT_MFMA 3     /* the correlation sums of every flip as one int8 matrix-core tile
-                                   per step (L <= 255 only; LABS_EINVAL above) */
+#define LABS_VARIANT_MFMA 3     /* the correlation sums of every flip as int8 matrix-core tiles:
+                                   one per step for L <= 255, two beyond (every L <= 383) */
 
 typedef struct labs_plan_opts {
     int32_t variant;          /* LABS_VARIANT_* */

@@ -855,7 +855,7 @@ static int resolve_opts(labs_walk_plan *p, const labs_plan_opts *in)
     }
     labs_plan_opts tuned{};
     const bool have = cache_lookup(maxL, &tuned);
-    // untuned default: the matrix-core scoring where it was measured faster (129 <= L <= 255),
+    // untuned default: the matrix-core scoring where it was measured faster (L >= 129),
     // the bit-sliced one elsewhere
     if (o.variant == LABS_VARIANT_AUTO)
         o.variant = have ? tuned.variant

@@ -79,10 +79,10 @@ hipError_t launch_isl_batch(int L, int count, const int8_t *s, int64_t *isl, dou
                             int32_t *psl, int32_t *corr, hipStream_t stream);
 hipError_t launch_enum_skew(int L, int32_t *isl, hipStream_t stream);
 int general_shape_for_length(int L);
-constexpr int kMfmaLMax = 255;     // the matrix-core scoring covers c <= 127
+constexpr int kMfmaLMax = 383;     // the matrix-core scoring covers every walk length
 constexpr int kMfmaAutoLMin = 129; // below it the bit-sliced scoring is as fast (measured)
 hipError_t launch_flip_scores_mfma(int L, int count, const uint32_t *x, int32_t *scores, hipStream_t stream);
-size_t mfma_wave_lds_bytes();
+size_t mfma_wave_lds_bytes(int shape); // per walk (shape < 0: mixed lengths)
 hipError_t launch_walk_general(int shape, WalkState *states, int32_t count, const int32_t *order, uint64_t *tables,
                                int32_t *trace, int32_t *scores, hipStream_t stream);
 hipError_t launch_pq_walk(int shape, WalkState *states, int32_t count, const int32_t *order, uint64_t *tables,

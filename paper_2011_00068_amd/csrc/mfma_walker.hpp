@@ -44,23 +44,28 @@ typedef int mfma_v4i __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) const uint32_t lds_cu32; // LDS words, read
 typedef __attribute__((address_space(3))) const uint64_t lds_cu64; // (8-byte aligned) LDS pairs, read
 
-constexpr int kMfmaSeqDwords = 64; // 256 bytes per string copy
-constexpr int kMfmaSeqStride = 66; // copies 2 dwords apart in bank order: the four copies read by one
-                                   // A load fall on two bank sets instead of one
-constexpr int kMfmaCDwords = 56;   // one copy of C': byte 20 + kappa - r in copy r, zero elsewhere
-constexpr int kMfmaCBytes = 4 * kMfmaCDwords;
-constexpr int kMfmaCWords = 128;   // C' at kappa (0 for kappa >= c; index c serves as the zero word)
-
-struct WaveLdsMfma {
-    uint32_t par[2][kParWords];     // bit a of par[p] = b_{2a+p} (0 past the sequence end)
-    uint32_t rev[2][kRevWords];     // bit a of rev[p] = bit (kNA-1-a) of par[p], 0 past kNA-1
-    uint32_t xw[kXWords];           // free bits (kept current by every commit)
-    uint32_t bestx[kXWords];        // free bits of the best state of the walk so far
-    int32_t book[8];                // the walk loop's rarely updated bookkeeping
-    int32_t C[kMfmaCWords];         // C'_kappa at index kappa
-    uint32_t sb[4][kMfmaSeqStride]; // +-1 byte copies of the A strings (first kMfmaSeqDwords used)
-    uint32_t cb[4][kMfmaCDwords];   // C' as int8, four copies shifted by 0..3 bytes
+// Per-wave LDS block.  The small layout serves c <= 127 (one tile, four strings); the big one
+// serves up to c = 191 (a second tile for half indices 64..127 with two more strings, longer
+// strings and C' copies) and every walker of a mixed-length launch.
+template <int NSTR, int SEQ_DWORDS, int SEQ_STRIDE, int C_DWORDS, int C_WORDS>
+struct WaveLdsMfmaT {
+    static constexpr int kStrings = NSTR;
+    static constexpr int kSeqDwords = SEQ_DWORDS; // string bytes used: 4 kSeqDwords
+    static constexpr int kCDwords = C_DWORDS;     // one copy of C': byte 20 + kappa - r in copy r
+    static constexpr int kCWords = C_WORDS;       // C' at kappa (0 for kappa >= c; C'_c is the zero word)
+    uint32_t par[2][kParWords];       // bit a of par[p] = b_{2a+p} (0 past the sequence end)
+    uint32_t rev[2][kRevWords];       // bit a of rev[p] = bit (kNA-1-a) of par[p], 0 past kNA-1
+    uint32_t xw[kXWords];             // free bits (kept current by every commit)
+    uint32_t bestx[kXWords];          // free bits of the best state of the walk so far
+    int32_t book[8];                  // the walk loop's rarely updated bookkeeping
+    int32_t C[C_WORDS];               // C'_kappa at index kappa
+    uint32_t sb[NSTR][SEQ_STRIDE];    // +-1 byte strings of the A operands (strides 2 dwords past a
+                                      // multiple of 32: the copies read by one load use two bank sets)
+    uint32_t cb[4][C_DWORDS];         // C' as int8, four copies shifted by 0..3 bytes
 };
+// strings: kind p (s^p), kind 2+p (s^p_{63-u}) and, big only, kind 4+p (s^p_{127-u})
+using WaveLdsMfma = WaveLdsMfmaT<4, 64, 66, 56, 128>;
+using WaveLdsMfmaBig = WaveLdsMfmaT<6, 92, 98, 74, 192>;
 
 __device__ __forceinline__ uint32_t nibble_bytes(uint32_t nib)
 {
@@ -71,17 +76,23 @@ __device__ __forceinline__ uint32_t nibble_bytes(uint32_t nib)
 // Per-lane constants of one owned flip (they depend only on L and j).
 struct MfmaFlip {
     const int32_t *c_kd; // C'_{kappa_d}; the zero word C'_c for the centre (and past it)
-    uint32_t m0, m1;     // both-sided shifts but kappa_d: bits kappa < nq, kappa != kappa_d
+    uint32_t m0, m1, m2; // both-sided shifts but kappa_d: bits kappa < nq, kappa != kappa_d
     int32_t hc;          // np + 3 nq - 1 - 2 [q_d valid]; nq for the centre
 };
 
-template <int KW>
+// KW: shift window words (c <= 32 KW); BIG: flips up to c = 191 (two tiles, four flips per
+// lane: j = 2 l + g for g < 2 and j = 128 + 2 l + (g - 2) for g >= 2, i.e. half index l and
+// 64 + l); LdsT: the LDS layout (big whenever BIG, or in a mixed-length launch).
+template <int KW, bool BIG = false, class LdsT = WaveLdsMfma>
 struct MfmaWalker {
-    static constexpr int kG = 2;
-    static constexpr int G = 2;
+    static constexpr int G = BIG ? 4 : 2;
+    static constexpr int kG = G;
     static constexpr int QR = (KW + 1) / 2;
     static constexpr int KB = (32 * KW + 16 + 63) / 64; // K blocks of 64
-    using Lds = WaveLdsMfma;
+    static constexpr int kCBytes = 4 * LdsT::kCDwords;  // distance of the C' copies
+    using Lds = LdsT;
+    static_assert(!BIG || LdsT::kStrings == 6, "the second tile needs the big layout");
+    static_assert(64 * KB + (BIG ? 112 : 48) <= 4 * LdsT::kSeqDwords, "A windows past the strings");
 
     int L, c, n;
     int lane;
@@ -92,15 +103,16 @@ struct MfmaWalker {
     int32_t Cv[QR];
     int32_t mult[G];     // factor of T_j: -8 s_j (-4 s_c for the centre, 0 past it)
     int planes;
-    int32_t eps8[G];     // 8 (-1)^(c-j) for j of parity g (uniform)
+    int32_t eps8[2];     // 8 (-1)^(c-j) for j of parity 0 / 1 (uniform)
     Lds *lds;
     const uint64_t *zk;
     MfmaFlip fc[G];
-    uint32_t ta, tb; // LDS addresses of this lane's A and B words of K block 0 (see init_lanes())
+    uint32_t ta, tb;   // LDS addresses of this lane's A and B words of K block 0 (see init_lanes())
+    uint32_t ta2;      // the same for the second tile's A operand (BIG)
     uint32_t wpa, wqa; // LDS addresses of the first window words of par[0] and rev[0] (see score())
     int32_t bsrc;      // ds_bpermute source of Z: lane 63 - lane
 
-    __device__ __forceinline__ int flip(int g) const { return 2 * lane + g; }
+    __device__ __forceinline__ int flip(int g) const { return (g < 2 ? 0 : 128) + 2 * lane + (g & 1); }
 
     __device__ __forceinline__ uint32_t *x_lds() const { return lds->xw; }
     __device__ __forceinline__ uint32_t *best_lds() const { return lds->bestx; }
@@ -118,42 +130,50 @@ struct MfmaWalker {
     __device__ __forceinline__ void init_lanes(int ln)
     {
         {
-            // Lane (slice, nn) of the tile needs A bytes S_kind[t0 + 16 ib ..] and the 16 bytes
+            // Lane (slice, nn) of a tile needs A bytes S_kind[t0 + 16 ib ..] and the 16 bytes
             // C'_{i0 .. i0+15}, i0 = t0 - 1 - nn, t0 = 16 slice + 64 kb; copy r = (i0 + 20) mod 4 of
-            // C' holds them from a dword boundary.  K block kb is 16 dwords further in both.
+            // C' holds them from a dword boundary.  K block kb is 16 dwords further in both.  The
+            // second tile (half indices 64 + h) reads kinds 0/1 64 bytes further and, for kinds
+            // 2/3, the strings s^p_{127-u}.
             const int nn = ln & 15, slice = ln >> 4;
             const int kind = ln & 3, ib = (ln & 15) >> 2;
             const int r = (3 - nn) & 3;
             ta = (uint32_t)(uintptr_t)&lds->sb[kind][4 * (slice + ib)];
+            ta2 = BIG ? (uint32_t)(uintptr_t)&lds->sb[kind < 2 ? kind : kind + 2][4 * (slice + ib) + (kind < 2 ? 16 : 0)] : 0u;
             tb = (uint32_t)(uintptr_t)&lds->cb[r][(16 * slice - 1 - nn + 20 - r) >> 2];
-            // window words of the both-sided shifts kappa < nq = ln <= 63: the p window starts at
-            // bit h+1 of par[g], the q window at bit kNA-h of rev[g]
+            // window words of the both-sided shifts kappa < nq (nq = ln, or 64 + ln): the p window
+            // starts at bit h+1 of par[g], the q window at bit kNA-h of rev[g]
             wpa = (uint32_t)(uintptr_t)&lds->par[0][(ln + 1) >> 5];
             wqa = (uint32_t)(uintptr_t)&lds->rev[0][(kNA - ln) >> 5];
             bsrc = (63 - ln) << 2;
             // whole addresses, so that every load is one base register plus an offset
             asm volatile("" : "+v"(ta), "+v"(tb), "+v"(wpa), "+v"(wqa), "+v"(bsrc));
+            if constexpr (BIG)
+                asm volatile("" : "+v"(ta2));
         }
 #pragma unroll
         for (int g = 0; g < G; g++) {
-            const int j = 2 * ln + g;
-            const int nq = ln;
+            const int j = (g < 2 ? 0 : 128) + 2 * ln + (g & 1);
+            const int nq = j >> 1;
             const int np = c - ((j + 1) >> 1);
             MfmaFlip &f = fc[g];
             if (j < c) {
-                const int kd = c - 1 - j;
+                const int kd = c - 1 - j; // <= 62 for the second tile's flips
                 const bool qdv = kd < nq;
-                uint64_t m = (1ull << nq) - 1ull; // nq <= 63
+                // bits kappa < nq (nq <= 63, or 64 <= nq <= 95 in the second tile)
+                uint64_t m = g < 2 ? (1ull << nq) - 1ull : ~0ull;
                 if (qdv)
                     m &= ~(1ull << kd);
                 f.c_kd = &lds->C[kd];
                 f.m0 = (uint32_t)m;
                 f.m1 = (uint32_t)(m >> 32);
+                f.m2 = g < 2 ? 0u : (1u << (nq - 64)) - 1u;
                 f.hc = np + 3 * nq - 1 - (qdv ? 2 : 0);
             } else {
                 f.c_kd = &lds->C[c];
                 f.m0 = 0u;
                 f.m1 = 0u;
+                f.m2 = 0u;
                 f.hc = nq;
             }
         }
@@ -198,33 +218,37 @@ struct MfmaWalker {
             lds->par[lane & 1][6 + (lane >> 1)] = 0u;
         if (lane < 2 * (kRevWords - 6))
             lds->rev[lane & 1][6 + (lane >> 1)] = 0u;
-        for (int i = lane; i < 4 * kMfmaCDwords; i += kWave)
-            lds->cb[i / kMfmaCDwords][i % kMfmaCDwords] = 0u;
+        for (int i = lane; i < 4 * LdsT::kCDwords; i += kWave)
+            lds->cb[i / LdsT::kCDwords][i % LdsT::kCDwords] = 0u;
         // prepare() writes C'_kappa for kappa < 64 QR; the zero word C'_c may lie past that (c = 64)
-        for (int i = lane; i < kMfmaCWords; i += kWave)
+        for (int i = lane; i < LdsT::kCWords; i += kWave)
             lds->C[i] = 0;
         lds_fence();
-        // +-1 byte copies of the strings: kind p from par[p] at half index u = 4 lane + i, kind
-        // 2+p from rev[p] at bit 128 + u (= s^p_{63-u}); 0 where the half index is outside the
-        // sequence (2 u' + p > L - 1, or u' < 0)
+        // +-1 byte strings: kind p from par[p] at half index u = 4 i + b, kind 2+p from rev[p] at
+        // bit 128 + u (= s^p_{63-u}), kind 4+p from rev[p] at bit 64 + u (= s^p_{127-u}); 0 where
+        // the half index is outside the sequence
+        for (int i = lane; i < LdsT::kSeqDwords; i += kWave) {
 #pragma unroll
-        for (int k4 = 0; k4 < 4; k4++) {
-            const int p = k4 & 1;
-            const int bitpos = (k4 < 2 ? 0 : 128) + 4 * lane;
-            const uint32_t word = (k4 < 2) ? lds->par[p][bitpos >> 5] : lds->rev[p][bitpos >> 5];
-            uint32_t valid = 0;
+            for (int k4 = 0; k4 < LdsT::kStrings; k4++) {
+                const int p = k4 & 1, kind = k4 >> 1;
+                const int bitpos = (kind == 0 ? 0 : (kind == 1 ? 128 : 64)) + 4 * i;
+                uint32_t valid = 0;
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
-                const int u = (k4 < 2) ? 4 * lane + i : 63 - (4 * lane + i);
-                valid |= (u >= 0 && 2 * u + p <= L - 1) ? 1u << i : 0u;
+                for (int b = 0; b < 4; b++) {
+                    const int u = kind == 0 ? 4 * i + b : (kind == 1 ? 63 : 127) - (4 * i + b);
+                    valid |= (u >= 0 && 2 * u + p <= L - 1) ? 1u << b : 0u;
+                }
+                uint32_t word = 0;
+                if (valid) // (the word index stays inside the strings where any byte is valid)
+                    word = kind == 0 ? lds->par[p][bitpos >> 5] : lds->rev[p][bitpos >> 5];
+                const uint32_t bits = (word >> (bitpos & 31)) & valid;
+                lds->sb[k4][i] = nibble_bytes(valid) | (nibble_bytes(bits) * 0xFEu);
             }
-            const uint32_t bits = (word >> (bitpos & 31)) & valid;
-            lds->sb[k4][lane] = nibble_bytes(valid) | (nibble_bytes(bits) * 0xFEu);
         }
         uint32_t sb2[G];
 #pragma unroll
         for (int g = 0; g < G; g++) {
-            const int j = 2 * lane + g;
+            const int j = flip(g);
             sb2[g] = (j <= c) ? seq_bit(j) : 0u;
             const int32_t s = 1 - 2 * (int32_t)sb2[g];
             mult[g] = j < c ? -8 * s : (j == c ? -4 * s : 0);
@@ -258,7 +282,7 @@ struct MfmaWalker {
         uint64_t hz = 0;
 #pragma unroll
         for (int g = 0; g < G; g++) {
-            const int j = 2 * lane + g;
+            const int j = flip(g);
             if (j <= c && sb2[g])
                 hz ^= zk[j];
         }
@@ -274,9 +298,11 @@ struct MfmaWalker {
 #pragma unroll
         for (int q = 0; q < QR; q++)
             lds->C[lane + 64 * q] = Cv[q];
-        // some |C'_kappa| above the int8 range?  |C'_kappa| <= L - 2 - 2 kappa <= 127 from kappa = 63
-        // on, so only the first 64 shifts need the test
-        const bool wide = (uint32_t)(Cv[0] + 128) > 255u;
+        // some |C'_kappa| above the int8 range?  |C'_kappa| <= L - 2 - 2 kappa <= 127 from
+        // kappa = (L - 129) / 2 on: the first 64 shifts for L <= 255, the first 128 beyond
+        bool wide = (uint32_t)(Cv[0] + 128) > 255u;
+        if constexpr (BIG)
+            wide = wide || (uint32_t)(Cv[1] + 128) > 255u;
         planes = ballot(wide) != 0ull ? 9 : 8; // only "fits int8 or not" is used
         put_c(0);
         if (planes > 8)
@@ -285,7 +311,7 @@ struct MfmaWalker {
     }
 
     // C' bytes into the four shifted copies: part 0 C' itself, part 1 its low six bits (0..63),
-    // part 2 C' >> 6 (-4..3 for |C'| <= 253).
+    // part 2 C' >> 6 (-6..5 for |C'| <= 381).
     __device__ __forceinline__ void put_c(int part)
     {
         int8_t *cp = reinterpret_cast<int8_t *>(lds->cb[0]) + 20 + lane;
@@ -294,16 +320,17 @@ struct MfmaWalker {
             const int32_t v = part == 0 ? Cv[q] : (part == 1 ? (Cv[q] & 63) : (Cv[q] >> 6));
 #pragma unroll
             for (int r = 0; r < 4; r++)
-                cp[64 * q + r * (kMfmaCBytes - 1)] = (int8_t)v;
+                cp[64 * q + r * (kCBytes - 1)] = (int8_t)v;
         }
     }
 
-    // One K-sweep of the tile with the C' bytes now in the copies.
-    __device__ __forceinline__ mfma_v4i tile() const
+    // One K-sweep of a tile (A operand at LDS address a_addr) with the C' bytes now in the
+    // copies.
+    __device__ __forceinline__ mfma_v4i tile(uint32_t a_addr) const
     {
-        // A windows start on 8-byte boundaries (the string copies are 264 bytes apart), B windows on
+        // A windows start on 8-byte boundaries (the strings are 8-byte aligned), B windows on
         // dword boundaries
-        const lds_cu64 *ap = (const lds_cu64 *)(uintptr_t)ta;
+        const lds_cu64 *ap = (const lds_cu64 *)(uintptr_t)a_addr;
         const lds_cu32 *bp = (const lds_cu32 *)(uintptr_t)tb;
         // every operand load first, so that one LDS latency covers the whole K sweep
         mfma_v4i a[KB], b[KB];
@@ -320,6 +347,22 @@ struct MfmaWalker {
         return acc;
     }
 
+    // the product of a tile, with the second sweep of a wide C' (C' = 64 hi + lo)
+    __device__ __forceinline__ mfma_v4i tile_all(uint32_t a_addr)
+    {
+        mfma_v4i d = tile(a_addr);
+        if (planes > 8) {
+            // the copies held lo (the caller rewrites them with lo again afterwards when several
+            // tiles use them); the wave's LDS operations run in order, so the reads above complete
+            // before the hi bytes overwrite them
+            put_c(2);
+            lds_fence();
+            const mfma_v4i hi = tile(a_addr);
+            d = d + hi * 64;
+        }
+        return d;
+    }
+
     __device__ __forceinline__ void score(int32_t (&isl_j)[G])
     {
         const int lane = this->lane;
@@ -333,50 +376,63 @@ struct MfmaWalker {
 #pragma unroll
             for (int g = 0; g < G; g++) {
                 const MfmaFlip &f = fc[g];
-                const lds_cu32 *wpg = wp + g * kParWords;
-                const lds_cu32 *wqg = wq + g * kRevWords;
+                // the second tile's windows start 64 bits further in par, 64 bits earlier in rev
+                const lds_cu32 *wpg = wp + (g & 1) * kParWords + (g < 2 ? 0 : 2);
+                const lds_cu32 *wqg = wq + (g & 1) * kRevWords - (g < 2 ? 0 : 2);
                 const uint32_t wp0 = funnel(wpg[1], wpg[0], (int)sp);
                 const uint32_t wp1 = funnel(wpg[2], wpg[1], (int)sp);
                 const uint32_t wq0 = funnel(wqg[1], wqg[0], (int)(1u - sp));
                 const uint32_t wq1 = funnel(wqg[2], wqg[1], (int)(1u - sp));
                 uint32_t rc = bcnt_acc((wp0 ^ wq0) & f.m0, 0u);
                 rc = bcnt_acc((wp1 ^ wq1) & f.m1, rc);
-                // |C'| <= 253: a 24-bit product
-                base[g] = mad24((int32_t)rc, -64, isl + 16 * f.hc) + __mul24(eps8[g], *f.c_kd);
+                if (g >= 2) {
+                    const uint32_t wp2 = funnel(wpg[3], wpg[2], (int)sp);
+                    const uint32_t wq2 = funnel(wqg[3], wqg[2], (int)(1u - sp));
+                    rc = bcnt_acc((wp2 ^ wq2) & f.m2, rc);
+                }
+                // |C'| <= 381: a 24-bit product
+                base[g] = mad24((int32_t)rc, -64, isl + 16 * f.hc) + __mul24(eps8[g & 1], *f.c_kd);
             }
         }
-        mfma_v4i d = tile();
-        if (planes > 8) {
-            // C' = 64 hi + lo: the copies held lo; the wave's LDS operations run in order, so the
-            // reads above complete before the hi bytes overwrite them
-            put_c(2);
-            lds_fence();
-            const mfma_v4i hi = tile();
-            d = d + hi * 64;
-        }
-        // Z for h = lane sits in lane 63 - lane; |T| <= 128 * 253: a 24-bit product
+        const mfma_v4i d = tile_all(ta);
+        // Z for h = lane sits in lane 63 - lane; |T| <= 191 * 381: 24-bit products
         isl_j[0] = mad24(mult[0], d[0] + __builtin_amdgcn_ds_bpermute(bsrc, d[2]), base[0]);
         isl_j[1] = mad24(mult[1], d[1] + __builtin_amdgcn_ds_bpermute(bsrc, d[3]), base[1]);
+        if constexpr (BIG) {
+            if (planes > 8) // the copies hold hi now: lo again for the second tile
+                put_c(1);
+            const mfma_v4i d2 = tile_all(ta2);
+            // second tile: Y for half index 64 + lane, Z for 127 - lane (brought from lane 63 - lane)
+            isl_j[2] = mad24(mult[2], d2[0] + __builtin_amdgcn_ds_bpermute(bsrc, d2[2]), base[2]);
+            isl_j[3] = mad24(mult[3], d2[1] + __builtin_amdgcn_ds_bpermute(bsrc, d2[3]), base[3]);
+        }
     }
 
     template <bool REG_X = true>
     __device__ __forceinline__ void commit(int js, int32_t isl_new)
     {
         const int lane = this->lane;
+        const int ol = (js & 127) >> 1;              // the lane that scores js
+        const int slot = (js >> 7) * 2 + (js & 1);   // and its slot
         // the sign of s_js from the owner lane's mult
-        const int32_t m0 = __builtin_amdgcn_readlane(mult[0], js >> 1);
-        const int32_t m1 = __builtin_amdgcn_readlane(mult[1], js >> 1);
-        const uint32_t bjs = ((js & 1) ? m1 : m0) > 0 ? 1u : 0u;
+        int32_t mj = __builtin_amdgcn_readlane(mult[0], ol);
+#pragma unroll
+        for (int g = 1; g < G; g++)
+            mj = slot == g ? __builtin_amdgcn_readlane(mult[g], ol) : mj;
+        const uint32_t bjs = mj > 0 ? 1u : 0u;
         const int hjs = js >> 1;
         const int pis = js & 1;
         const int nps = (js == c) ? 0 : c - ((js + 1) >> 1);
         const int kds = (js == c) ? -1 : c - 1 - js;
         // dC'_kappa = -4 s_js (p_kappa + q_kappa), p without the excluded shift kappa_d, read from
-        // the +-1 byte strings (0 past either end, so lanes with kappa >= c add nothing); at the
-        // centre p = q and u = q, so the factor is halved instead
+        // the +-1 byte strings (0 past either end, so lanes with kappa >= c add nothing): p from
+        // s^p at hjs + 1 + kappa, q = s^p_{hjs-1-kappa} from the reversed string (s^p_{63-u}, or
+        // s^p_{127-u} when half indices reach past 64); at the centre p = q and u = q, so the
+        // factor is halved instead
         const int32_t f = (js == c) ? (bjs ? 2 : -2) : (bjs ? 4 : -4);
         const int8_t *pb = reinterpret_cast<const int8_t *>(lds->sb[pis]) + hjs + 1 + lane;
-        const int8_t *qb = reinterpret_cast<const int8_t *>(lds->sb[2 + pis]) + 64 - hjs + lane;
+        const int8_t *qb = BIG ? reinterpret_cast<const int8_t *>(lds->sb[4 + pis]) + 128 - hjs + lane
+                               : reinterpret_cast<const int8_t *>(lds->sb[2 + pis]) + 64 - hjs + lane;
 #pragma unroll
         for (int q = 0; q < QR; q++) {
             const int32_t pv = (lane + 64 * q == kds) ? 0 : (int32_t)pb[64 * q];
@@ -384,8 +440,8 @@ struct MfmaWalker {
         }
         lds_fence();
         // the flipped symbol and its mirror (m = 2c - js, half index nps) in the bit strings and
-        // in the +-1 byte copies (kind p at byte a, kind 2+p at byte 63 - a when a <= 63; 0x01 and
-        // 0xFF swap under xor 0xFE)
+        // in the +-1 byte strings (kind p at byte a, kind 2+p at byte 63 - a when a <= 63, kind 4+p
+        // at byte 127 - a; 0x01 and 0xFF swap under xor 0xFE)
         // (lane 0: js, lane 1: the mirror; toggles that do not apply xor 0, so there is one branch)
         if (lane < (js != c ? 2 : 1)) {
             const int a = lane ? nps : hjs;
@@ -395,14 +451,19 @@ struct MfmaWalker {
             atomicXor(&lds->sb[pis][a >> 2], 0xFEu << (8 * (a & 3)));
             const int u = 63 - a;
             atomicXor(&lds->sb[2 + pis][max(u, 0) >> 2], u >= 0 ? 0xFEu << (8 * (u & 3)) : 0u);
+            if constexpr (BIG) {
+                const int u2 = 127 - a; // a <= 95
+                atomicXor(&lds->sb[4 + pis][u2 >> 2], 0xFEu << (8 * (u2 & 3)));
+            }
             // the free bit itself (lane 1 xors 0 into a neighbouring word: a lane-varying address keeps
             // the compiler from turning the toggle into a cross-lane reduction)
             atomicXor(&lds->xw[(js >> 5) ^ lane], lane == 0 ? 1u << (js & 31) : 0u);
         }
         lds_fence();
-        const bool own = lane == (js >> 1); // this lane scores js
-        mult[0] = (own && !(js & 1)) ? -mult[0] : mult[0];
-        mult[1] = (own && (js & 1)) ? -mult[1] : mult[1];
+        const bool own = lane == ol;
+#pragma unroll
+        for (int g = 0; g < G; g++)
+            mult[g] = (own && slot == g) ? -mult[g] : mult[g];
         if (REG_X)
             xflip_uniform(x, js);
         x0 ^= js < 32 ? 1u << js : 0u;

@@ -126,9 +126,11 @@ void summarise(labs_server *S, Job &j)
 void scheduler(labs_server *S)
 {
     WalkLaunch lp{};
-    lp.variant = LABS_VARIANT_BITSLICE;
+    // the mixed-length matrix-core kernel serves every length (measured faster than the
+    // bit-sliced one on mixed batches of L = 201..303)
+    lp.variant = LABS_VARIANT_MFMA;
     lp.waves_per_block = 1;
-    lp.probe_width = 1; // the bit-sliced walker's faster setting (measured)
+    lp.probe_width = 2;
     lp.shape = -1;
     lp.chunk = S->opts.steps_per_tick;
     lp.persistent = 0;

@@ -1035,6 +1035,6 @@ WalkKernel pick_walk_kernel_bits_pw1(int shape);
 WalkKernel pick_walk_kernel_bits_pw2(int shape);
 WalkKernel pick_walk_kernel_direct_pw1(int shape);
 WalkKernel pick_walk_kernel_direct_pw2(int shape);
-WalkKernel pick_walk_kernel_mfma(int shape); // nullptr for shapes with c > 127
+WalkKernel pick_walk_kernel_mfma(int shape);
 
 } // namespace liblabs

@@ -40,17 +40,17 @@ static WalkKernel pick_kernel(const WalkLaunch &lp)
                                          : pick_walk_kernel_bits_pw1(lp.shape));
 }
 
-static size_t wave_lds_bytes(int variant)
+static size_t wave_lds_bytes(int variant, int shape)
 {
     if (variant == LABS_VARIANT_MFMA)
-        return mfma_wave_lds_bytes();
+        return mfma_wave_lds_bytes(shape);
     return variant == LABS_VARIANT_DIRECT ? sizeof(WaveLdsDirect) : sizeof(WaveLdsBits);
 }
 
 int resident_walk_waves(const WalkLaunch &lp)
 {
     const int wpb = lp.waves_per_block;
-    const size_t lds = (size_t)wpb * wave_lds_bytes(lp.variant);
+    const size_t lds = (size_t)wpb * wave_lds_bytes(lp.variant, lp.shape);
     int blocks = 0, dev = 0, cus = 0;
     if (!pick_kernel(lp))
         return 0;
@@ -72,7 +72,7 @@ hipError_t launch_walk(const WalkLaunch &lp, WalkState *states, int32_t n_walks,
         return hipErrorInvalidValue;
     if (wpb < 1 || wpb > kMaxWavesPerBlock)
         return hipErrorInvalidConfiguration; // the kernel is compiled for at most 8 waves per block
-    const size_t lds = (size_t)wpb * wave_lds_bytes(lp.variant);
+    const size_t lds = (size_t)wpb * wave_lds_bytes(lp.variant, lp.shape);
     int blocks;
     int32_t *ctr = nullptr;
     if (lp.persistent) {

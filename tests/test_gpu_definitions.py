@@ -103,11 +103,9 @@ ALL_L = list(range(3, 384, 2))
 
 @pytest.mark.parametrize("variant", [1, 2, 3], ids=["bitslice", "direct", "mfma"])
 def test_flip_scores_every_length(labs, variant):
-    # every odd L in [3, 383] (255 for the matrix-core form), random states plus the all-+1 and
-    # all--1 states (whose correlations exceed the int8 range)
+    # every odd L in [3, 383] (the matrix-core form: one tile up to 255, two beyond), random
+    # states plus the all-+1 and all--1 states (whose correlations exceed the int8 range)
     for L in ALL_L:
-        if variant == 3 and L > 255:
-            continue
         n = (L + 1) // 2
         rng = random.Random(L * 7 + variant)
         xs = [rng.getrandbits(n) for _ in range(3)] + [0, (1 << n) - 1]
@@ -123,15 +121,17 @@ def test_flip_scores_brute_force_sample(labs):
         n = (L + 1) // 2
         rng = random.Random(L)
         xs = [rng.getrandbits(n)]
-        for variant in ((1, 2, 3) if L <= 255 else (1, 2)):
+        for variant in (1, 2, 3):
             got = labs.flip_scores(L, xs, variant=variant).cpu().numpy()
             assert np.array_equal(got[0], o.flip_scores(L, xs[0], brute=True)), (L, variant)
 
 
-def test_mfma_variant_rejects_long_sequences(labs):
-    with pytest.raises(labs.LabsError) as e:
-        labs.flip_scores(257, [1], variant=3)
-    assert e.value.code == labs.LABS_EINVAL
+def test_flip_scores_rejects_bad_lengths(labs):
+    for variant in (1, 3):
+        for L in (385, 254):
+            with pytest.raises(labs.LabsError) as e:
+                labs.flip_scores(L, [1], variant=variant)
+            assert e.value.code == labs.LABS_EINVAL
 
 
 def test_flip_scores_table1(labs):
