@@ -268,6 +268,26 @@ def counter_summary():
     return t
 
 
+def lds_summary(labs, cnt):
+    """The walk kernel against the LDS roof: the share of cycles in which the LDS pipe of a compute
+    unit is busy (rocprofv3 SQ_LDS_IDX_ACTIVE over GRBM_GUI_ACTIVE cycles, of which bank-conflict
+    cycles), from the committed counter summary, next to the device's LDS read bandwidth measured
+    now (8- and 16-byte reads per lane; the walk kernels issue 1- to 8-byte accesses, which move at
+    most 128 bytes per cycle per compute unit)."""
+    out = {"active_frac": None, "bank_conflict_frac": None, "active_cycles_per_step": None,
+           "peak_read_8B_TBps": None, "peak_read_16B_TBps": None}
+    if cnt and "lds_active_frac" in cnt:
+        out["active_frac"] = cnt["lds_active_frac"]
+        out["bank_conflict_frac"] = cnt["lds_bank_conflict_frac"]
+        out["active_cycles_per_step"] = cnt["lds_active_cycles_per_step"]
+    try:
+        out["peak_read_8B_TBps"] = labs.probe_lds_read(8)["bytes_per_s"] / 1e12
+        out["peak_read_16B_TBps"] = labs.probe_lds_read(16)["bytes_per_s"] / 1e12
+    except labs.LabsError as e:
+        print(f"LDS probe failed: {e}", file=sys.stderr)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -282,7 +302,17 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--probe-lds", action="store_true",
+                    help="only measure the LDS read bandwidth (4-, 8- and 16-byte reads per lane) and exit")
     args = ap.parse_args()
+    if args.probe_lds:
+        import paper_2011_00068_amd as labs
+
+        for w in (4, 8, 16):
+            r = labs.probe_lds_read(w)
+            print(json.dumps({"lds_read_bytes_per_lane": w, "bytes_per_s": r["bytes_per_s"], "ms": r["ms"]}),
+                  flush=True)
+        return
     if args.calibrate_copy:
         import torch
 
@@ -341,7 +371,8 @@ def main():
                 "counter_valu_issue_frac": cnt["valu_issue_busy_frac"] if cnt else None,
                 "counter_valu_insts_per_step": cnt["valu_insts_per_step"] if cnt else None,
                 "counter_salu_issue_frac": cnt.get("salu_issue_busy_frac") if cnt else None,
-                "counter_mfma_insts_per_step": cnt.get("mfma_insts_per_step") if cnt else None}
+                "counter_mfma_insts_per_step": cnt.get("mfma_insts_per_step") if cnt else None,
+                "lds": lds_summary(labs, cnt)}
 
     line = {
         "metric": "flip-evals/s at L=255 (batched walks, % INT32 VALU peak); p50 time-to-F>=8",

@@ -59,6 +59,14 @@ const char *labs_last_error(void);
  * shader clock (kHz).  Returns LABS_EDEVICE when no gfx950 device is visible. */
 int labs_device_info(char *name, int32_t cap, int32_t *compute_units, int32_t *clock_khz);
 
+/* Measurement aid (no operation of the paper): the LDS read bandwidth of the device, for the LDS
+ * roof of the walk kernels.  A kernel of 256-thread blocks (16 per compute unit, 64 KB of LDS
+ * each) streams conflict-free reads of bytes_per_lane = 4, 8 or 16 bytes per lane out of LDS;
+ * *bytes_per_s receives the bytes read per second of the fastest of five timed launches (HIP
+ * events on the default stream), *ms_out (may be NULL) that launch's time.  Synchronous; allocates
+ * and frees a small device buffer.  LABS_EINVAL for another width or a NULL bytes_per_s. */
+int labs_probe_lds_read(int32_t bytes_per_lane, double *bytes_per_s, double *ms_out);
+
 /* ---------------------------------------------------------------------------------------------
  * Definitions of Section 1.
  * ------------------------------------------------------------------------------------------- */

@@ -41,7 +41,7 @@ JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_CANCELLED = 0, 1, 2, 3
 
 # Every symbol include/labs.h declares (checked by the tests).
 EXPORTS = [
-    "labs_strerror", "labs_last_error", "labs_device_info",
+    "labs_strerror", "labs_last_error", "labs_device_info", "labs_probe_lds_read",
     "labs_isl", "labs_merit", "labs_isl_batch_dev", "labs_enum_skew_dev", "labs_enum_skew_min",
     "labs_flip_scores_dev",
     "labs_walk_batch", "labs_walk_plan_create", "labs_walk_plan_run", "labs_walk_plan_results",
@@ -182,6 +182,7 @@ def lib():
     L.labs_last_error.restype = ctypes.c_char_p
     L.labs_last_error.argtypes = []
     L.labs_device_info.argtypes = [ctypes.c_char_p, i32, P(i32), P(i32)]
+    L.labs_probe_lds_read.argtypes = [i32, P(ctypes.c_double), P(ctypes.c_double)]
     L.labs_isl.argtypes = [i32, vp, P(i64)]
     L.labs_merit.argtypes = [i32, vp, P(ctypes.c_double)]
     L.labs_isl_batch_dev.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp]
@@ -230,6 +231,16 @@ def device_info():
     cu, clk = ctypes.c_int32(), ctypes.c_int32()
     _check(lib().labs_device_info(name, 64, ctypes.byref(cu), ctypes.byref(clk)), "labs_device_info")
     return {"name": name.value.decode(), "compute_units": cu.value, "clock_khz": clk.value}
+
+
+def probe_lds_read(bytes_per_lane=8):
+    """LDS read bandwidth of the device in bytes/s for 4-, 8- or 16-byte reads per lane (a
+    measurement aid for the walk kernels' LDS roof; see labs_probe_lds_read)."""
+    bps = ctypes.c_double()
+    ms = ctypes.c_double()
+    _check(lib().labs_probe_lds_read(int(bytes_per_lane), ctypes.byref(bps), ctypes.byref(ms)),
+           "labs_probe_lds_read")
+    return {"bytes_per_s": bps.value, "ms": ms.value}
 
 
 # --- definitions -------------------------------------------------------------------------------

@@ -128,6 +128,52 @@ extern "C" int labs_device_info(char *name, int32_t cap, int32_t *compute_units,
     return LABS_OK;
 }
 
+extern "C" int labs_probe_lds_read(int32_t bytes_per_lane, double *bytes_per_s, double *ms_out)
+{
+    if (bytes_per_lane != 4 && bytes_per_lane != 8 && bytes_per_lane != 16)
+        return fail(LABS_EINVAL, "bytes_per_lane = %d must be 4, 8 or 16", bytes_per_lane);
+    if (!bytes_per_s)
+        return fail(LABS_EINVAL, "NULL bytes_per_s");
+    int rc = check_device();
+    if (rc)
+        return rc;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+    // 16 blocks per CU (two resident at a time: 64 KB of LDS each); 0.5-1 ms a launch
+    const int blocks = 16 * std::max(1, prop.multiProcessorCount);
+    const int rounds = 512;
+    uint32_t *d_out = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    float best = -1.0f;
+    hipError_t e = hipMalloc(&d_out, (size_t)blocks * lds_probe_threads() * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = launch_lds_read_probe(bytes_per_lane, blocks, rounds, d_out, nullptr);
+    for (int r = 0; r < 5 && e == hipSuccess; r++) {
+        e = hipEventRecord(a, nullptr);
+        if (e == hipSuccess) e = launch_lds_read_probe(bytes_per_lane, blocks, rounds, d_out, nullptr);
+        if (e == hipSuccess) e = hipEventRecord(b, nullptr);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e == hipSuccess && (best < 0.0f || ms < best))
+            best = ms;
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (d_out) (void)hipFree(d_out);
+    if (e != hipSuccess)
+        return hip_fail(e, "labs_probe_lds_read");
+    if (best <= 0.0f)
+        return fail(LABS_EDEVICE, "labs_probe_lds_read: no measurable time");
+    *bytes_per_s = lds_probe_bytes(bytes_per_lane, blocks, rounds) / (best * 1e-3);
+    if (ms_out)
+        *ms_out = best;
+    return LABS_OK;
+}
+
 // =============================================================================================
 // Definitions: labs_isl, labs_merit, labs_isl_batch_dev, labs_enum_skew_dev.
 // =============================================================================================

@@ -78,6 +78,11 @@ hipError_t launch_flip_scores(int32_t variant, int L, int count, const uint32_t 
 hipError_t launch_isl_batch(int L, int count, const int8_t *s, int64_t *isl, double *F,
                             int32_t *psl, int32_t *corr, hipStream_t stream);
 hipError_t launch_enum_skew(int L, int32_t *isl, hipStream_t stream);
+// LDS read-bandwidth probe (probe_kernels.hip): blocks of lds_probe_threads() threads, each
+// lane reading bytes_per_lane (4, 8 or 16) bytes per read; out holds one word per thread.
+int lds_probe_threads();
+double lds_probe_bytes(int bytes_per_lane, int blocks, int rounds);
+hipError_t launch_lds_read_probe(int bytes_per_lane, int blocks, int rounds, uint32_t *out, hipStream_t stream);
 int general_shape_for_length(int L);
 constexpr int kMfmaLMax = 383;     // the matrix-core scoring covers every walk length
 constexpr int kMfmaAutoLMin = 129; // below it the bit-sliced scoring is as fast (measured)

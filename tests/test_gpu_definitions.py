@@ -140,3 +140,14 @@ def test_flip_scores_table1(labs):
         x = o.skew_bits(s)
         got = labs.flip_scores(row["L"], [x]).cpu().numpy()[0]
         assert np.array_equal(got, o.flip_scores(row["L"], x, brute=False))
+
+
+def test_probe_lds_read(labs):
+    # a measurement aid: positive, finite rates, and an error for an unsupported width
+    for w in (4, 8, 16):
+        r = labs.probe_lds_read(w)
+        assert 1e12 < r["bytes_per_s"] < 1e16
+        assert r["ms"] > 0
+    with pytest.raises(labs.LabsError) as e:
+        labs.probe_lds_read(12)
+    assert e.value.code == labs.LABS_EINVAL
