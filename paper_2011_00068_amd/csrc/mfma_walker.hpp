@@ -42,30 +42,53 @@ namespace liblabs {
 
 typedef int mfma_v4i __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) const uint32_t lds_cu32; // LDS words, read
-typedef __attribute__((address_space(3))) const uint64_t lds_cu64; // (8-byte aligned) LDS pairs, read
+typedef __attribute__((address_space(3))) const mfma_v4i lds_cv4;  // 16-byte aligned LDS quads, read
 
 // Per-wave LDS block.  The small layout serves c <= 127 (one tile, four strings); the big one
 // serves up to c = 191 (a second tile for half indices 64..127 with two more strings, longer
 // strings and C' copies) and every walker of a mixed-length launch.
-template <int NSTR, int SEQ_DWORDS, int SEQ_STRIDE, int C_DWORDS, int C_WORDS>
-struct WaveLdsMfmaT {
+//
+// The A operand of a tile is one 16-byte read per lane.  The 16 lanes of a row group read kinds
+// 0..3 x 4 windows of 16 bytes at the same K offset, so the strings that one tile reads must sit
+// at distinct multiples of 16 dwords modulo 64 for the group to cover 64 distinct banks.  Small
+// layout: strings 80 dwords apart (0, 16, 32, 48 mod 64).  Big layout: strings 0..3 144 apart
+// (0, 16, 32, 48), then strings 4 and 5 (the second tile's kinds 2/3, read beside kinds 0/1 at
+// +16 dwords, i.e. 16 and 32 mod 64) at 0 and 48 mod 64.
+template <int NSTR, int SEQ_DWORDS, int C_DWORDS, int C_WORDS>
+struct alignas(16) WaveLdsMfmaT {
     static constexpr int kStrings = NSTR;
     static constexpr int kSeqDwords = SEQ_DWORDS; // string bytes used: 4 kSeqDwords
     static constexpr int kCDwords = C_DWORDS;     // one copy of C': byte 20 + kappa - r in copy r
     static constexpr int kCWords = C_WORDS;       // C' at kappa (0 for kappa >= c; C'_c is the zero word)
+    // dword offset of string k in sbuf
+    __host__ __device__ static constexpr int str_off(int k)
+    {
+        return NSTR == 4 ? 80 * k : (k < 4 ? 144 * k : 576 + 112 * (k - 4));
+    }
+    static constexpr int kSbufDwords = str_off(NSTR - 1) + SEQ_DWORDS;
+    static_assert(NSTR == 4 || NSTR == 6, "four or six strings");
+    static_assert(NSTR == 4 ? (80 >= SEQ_DWORDS) : (144 >= SEQ_DWORDS && 112 >= SEQ_DWORDS &&
+                                                    576 >= 3 * 144 + SEQ_DWORDS),
+                  "strings overlap");
     uint32_t par[2][kParWords];       // bit a of par[p] = b_{2a+p} (0 past the sequence end)
     uint32_t rev[2][kRevWords];       // bit a of rev[p] = bit (kNA-1-a) of par[p], 0 past kNA-1
     uint32_t xw[kXWords];             // free bits (kept current by every commit)
     uint32_t bestx[kXWords];          // free bits of the best state of the walk so far
     int32_t book[8];                  // the walk loop's rarely updated bookkeeping
     int32_t C[C_WORDS];               // C'_kappa at index kappa
-    uint32_t sb[NSTR][SEQ_STRIDE];    // +-1 byte strings of the A operands (strides 2 dwords past a
-                                      // multiple of 32: the copies read by one load use two bank sets)
+    uint32_t sbuf[kSbufDwords];       // +-1 byte strings of the A operands, string k at str_off(k)
     uint32_t cb[4][C_DWORDS];         // C' as int8, four copies shifted by 0..3 bytes
+
+    __device__ __forceinline__ uint32_t *str(int k) { return sbuf + str_off(k); }
+    __device__ __forceinline__ const uint32_t *str(int k) const { return sbuf + str_off(k); }
 };
 // strings: kind p (s^p), kind 2+p (s^p_{63-u}) and, big only, kind 4+p (s^p_{127-u})
-using WaveLdsMfma = WaveLdsMfmaT<4, 64, 66, 56, 128>;
-using WaveLdsMfmaBig = WaveLdsMfmaT<6, 92, 98, 74, 192>;
+static_assert(sizeof(uint32_t) * (2 * kParWords + 2 * kRevWords + 2 * kXWords + 8) % 16 == 0,
+              "the C' table and the strings start 16-byte aligned");
+using WaveLdsMfma = WaveLdsMfmaT<4, 64, 56, 128>;
+using WaveLdsMfmaBig = WaveLdsMfmaT<6, 92, 74, 192>;
+static_assert(offsetof(WaveLdsMfma, sbuf) % 16 == 0 && offsetof(WaveLdsMfmaBig, sbuf) % 16 == 0,
+              "strings 16-byte aligned");
 
 __device__ __forceinline__ uint32_t nibble_bytes(uint32_t nib)
 {
@@ -138,8 +161,8 @@ struct MfmaWalker {
             const int nn = ln & 15, slice = ln >> 4;
             const int kind = ln & 3, ib = (ln & 15) >> 2;
             const int r = (3 - nn) & 3;
-            ta = (uint32_t)(uintptr_t)&lds->sb[kind][4 * (slice + ib)];
-            ta2 = BIG ? (uint32_t)(uintptr_t)&lds->sb[kind < 2 ? kind : kind + 2][4 * (slice + ib) + (kind < 2 ? 16 : 0)] : 0u;
+            ta = (uint32_t)(uintptr_t)(lds->str(kind) + 4 * (slice + ib));
+            ta2 = BIG ? (uint32_t)(uintptr_t)(lds->str(kind < 2 ? kind : kind + 2) + 4 * (slice + ib) + (kind < 2 ? 16 : 0)) : 0u;
             tb = (uint32_t)(uintptr_t)&lds->cb[r][(16 * slice - 1 - nn + 20 - r) >> 2];
             // window words of the both-sided shifts kappa < nq (nq = ln, or 64 + ln): the p window
             // starts at bit h+1 of par[g], the q window at bit kNA-h of rev[g]
@@ -242,7 +265,7 @@ struct MfmaWalker {
                 if (valid) // (the word index stays inside the strings where any byte is valid)
                     word = kind == 0 ? lds->par[p][bitpos >> 5] : lds->rev[p][bitpos >> 5];
                 const uint32_t bits = (word >> (bitpos & 31)) & valid;
-                lds->sb[k4][i] = nibble_bytes(valid) | (nibble_bytes(bits) * 0xFEu);
+                lds->str(k4)[i] = nibble_bytes(valid) | (nibble_bytes(bits) * 0xFEu);
             }
         }
         uint32_t sb2[G];
@@ -328,16 +351,14 @@ struct MfmaWalker {
     // copies.
     __device__ __forceinline__ mfma_v4i tile(uint32_t a_addr) const
     {
-        // A windows start on 8-byte boundaries (the strings are 8-byte aligned), B windows on
-        // dword boundaries
-        const lds_cu64 *ap = (const lds_cu64 *)(uintptr_t)a_addr;
+        // A windows start on 16-byte boundaries (one 16-byte read), B windows on dword boundaries
+        const lds_cv4 *ap4 = (const lds_cv4 *)(uintptr_t)a_addr;
         const lds_cu32 *bp = (const lds_cu32 *)(uintptr_t)tb;
         // every operand load first, so that one LDS latency covers the whole K sweep
         mfma_v4i a[KB], b[KB];
 #pragma unroll
         for (int kb = 0; kb < KB; kb++) {
-            const uint64_t a0 = ap[8 * kb], a1 = ap[8 * kb + 1];
-            a[kb] = mfma_v4i{(int)(uint32_t)a0, (int)(uint32_t)(a0 >> 32), (int)(uint32_t)a1, (int)(uint32_t)(a1 >> 32)};
+            a[kb] = ap4[4 * kb];
             b[kb] = mfma_v4i{(int)bp[16 * kb], (int)bp[16 * kb + 1], (int)bp[16 * kb + 2], (int)bp[16 * kb + 3]};
         }
         mfma_v4i acc = {0, 0, 0, 0};
@@ -430,9 +451,9 @@ struct MfmaWalker {
         // s^p_{127-u} when half indices reach past 64); at the centre p = q and u = q, so the
         // factor is halved instead
         const int32_t f = (js == c) ? (bjs ? 2 : -2) : (bjs ? 4 : -4);
-        const int8_t *pb = reinterpret_cast<const int8_t *>(lds->sb[pis]) + hjs + 1 + lane;
-        const int8_t *qb = BIG ? reinterpret_cast<const int8_t *>(lds->sb[4 + pis]) + 128 - hjs + lane
-                               : reinterpret_cast<const int8_t *>(lds->sb[2 + pis]) + 64 - hjs + lane;
+        const int8_t *pb = reinterpret_cast<const int8_t *>(lds->str(pis)) + hjs + 1 + lane;
+        const int8_t *qb = BIG ? reinterpret_cast<const int8_t *>(lds->str(4 + pis)) + 128 - hjs + lane
+                               : reinterpret_cast<const int8_t *>(lds->str(2 + pis)) + 64 - hjs + lane;
 #pragma unroll
         for (int q = 0; q < QR; q++) {
             const int32_t pv = (lane + 64 * q == kds) ? 0 : (int32_t)pb[64 * q];
@@ -448,12 +469,12 @@ struct MfmaWalker {
             atomicXor(&lds->par[pis][a >> 5], 1u << (a & 31));
             const int ar = kNA - 1 - a;
             atomicXor(&lds->rev[pis][ar >> 5], 1u << (ar & 31));
-            atomicXor(&lds->sb[pis][a >> 2], 0xFEu << (8 * (a & 3)));
+            atomicXor(lds->str(pis) + (a >> 2), 0xFEu << (8 * (a & 3)));
             const int u = 63 - a;
-            atomicXor(&lds->sb[2 + pis][max(u, 0) >> 2], u >= 0 ? 0xFEu << (8 * (u & 3)) : 0u);
+            atomicXor(lds->str(2 + pis) + (max(u, 0) >> 2), u >= 0 ? 0xFEu << (8 * (u & 3)) : 0u);
             if constexpr (BIG) {
                 const int u2 = 127 - a; // a <= 95
-                atomicXor(&lds->sb[4 + pis][u2 >> 2], 0xFEu << (8 * (u2 & 3)));
+                atomicXor(lds->str(4 + pis) + (u2 >> 2), 0xFEu << (8 * (u2 & 3)));
             }
             // the free bit itself (lane 1 xors 0 into a neighbouring word: a lane-varying address keeps
             // the compiler from turning the toggle into a cross-lane reduction)
