@@ -542,8 +542,9 @@ __device__ inline uint64_t slot_of(uint64_t hh, uint32_t x0, bool exact, int log
 // One walk, advanced until its budget, its target, or the launch's step limit.
 // ---------------------------------------------------------------------------------------------
 // TRACE = false: the walk records no trace and no scores, and the step loop carries no test for
-// them (run_walk below picks the instantiation).
-template <class W, int PW, bool TRACE>
+// them.  EXACT: 1 / 0 when the table is known to be addressed by the free bits (n <= table_log2)
+// / by the hash, -1 when the walk decides at run time (run_walk below picks the instantiation).
+template <class W, int PW, bool TRACE, int EXACT = -1>
 __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint64_t *__restrict__ tables,
                          int32_t *__restrict__ trace, int32_t *__restrict__ scores, int64_t chunk,
                          typename W::Lds *lds, const uint64_t *zk)
@@ -565,7 +566,7 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
     w.init_lanes(lane);
     const int L = w.L, n = w.n;
     const int tlog2 = su(ws.table_log2);
-    const bool exact = n <= tlog2;
+    const bool exact = EXACT >= 0 ? EXACT != 0 : n <= tlog2;
     const uint64_t seed = su(ws.seed);
     const uint32_t walk_id = su(ws.walk_id);
     const int64_t steps = su(ws.steps);
@@ -868,6 +869,15 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
     (void)L;
 }
 
+// free symbols n of a walk of length L for walker W (the flips it scores)
+template <class W>
+__device__ __forceinline__ int free_symbols(int L)
+{
+    W w;
+    w.set_length(L);
+    return w.n;
+}
+
 template <class W, int PW>
 __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *__restrict__ tables,
                          int32_t *__restrict__ trace, int32_t *__restrict__ scores, int64_t chunk,
@@ -875,8 +885,10 @@ __device__ __forceinline__ void run_walk(WalkState *__restrict__ wsp, uint64_t *
 {
     if (su(wsp->trace_offset) >= 0 || su(wsp->score_offset) >= 0)
         run_walk_impl<W, PW, true>(wsp, tables, trace, scores, chunk, lds, zk);
+    else if (free_symbols<W>(su(wsp->L)) <= su(wsp->table_log2))
+        run_walk_impl<W, PW, false, 1>(wsp, tables, trace, scores, chunk, lds, zk);
     else
-        run_walk_impl<W, PW, false>(wsp, tables, trace, scores, chunk, lds, zk);
+        run_walk_impl<W, PW, false, 0>(wsp, tables, trace, scores, chunk, lds, zk);
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -64,6 +64,20 @@ def test_targets_traps_exact_table(labs):
     assert got[1]["best_isl"] == 6 and got[1]["hit_step"] > 0
 
 
+def test_targets_traps_exact_table_untraced(labs):
+    # the same kinds of walks without traces (the step loop built without trace tests, for tables
+    # addressed by the free bits and by the hash)
+    cfgs = [
+        labs.make_cfg(4, SEED, 0, steps=60, table_log2=8),
+        labs.make_cfg(13, SEED, 1, steps=3000, table_log2=14, target_isl=6),
+        labs.make_cfg(20, SEED, 2, steps=1500, table_log2=22, restart_period=500),
+        labs.make_cfg(100, SEED, 3, steps=400, watch_isl=1600),
+    ]
+    got, _ = labs.general_walk_batch(cfgs)
+    for i, c in enumerate(cfgs):
+        assert_same(got[i], oracle_general(c), i)
+
+
 def test_mixed_lengths_and_batch_sample(labs):
     cfgs = [labs.make_cfg(L, SEED, w, steps=2000, table_log2=16) for L in (64, 101, 128, 192) for w in range(256)]
     got, _ = labs.general_walk_batch(cfgs)

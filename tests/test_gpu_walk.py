@@ -131,6 +131,9 @@ def test_restarts_traps_targets_untraced(labs):
         labs.make_cfg(255, SEED, 3, steps=300, restart_period=64, table_log2=10),
         labs.make_cfg(255, SEED, 3, steps=300, restart_period=64, table_log2=10, trace=True),
         labs.make_cfg(201, SEED, 5, steps=400, restart_period=150, watch_isl=3000),
+        # tables addressed by the free bits (n <= table_log2), untraced
+        labs.make_cfg(31, SEED, 0, steps=3000, table_log2=16),
+        labs.make_cfg(41, SEED, 2, steps=2000, table_log2=21, restart_period=700),
     ]
     for variant in (1, 2, 3):
         for opt in (dict(), dict(steps_per_launch=61)):
