@@ -535,7 +535,8 @@ __device__ inline void clear_table(uint64_t *T, int log2)
 
 __device__ inline uint64_t slot_of(uint64_t hh, uint32_t x0, bool exact, int log2)
 {
-    return exact ? (uint64_t)x0 : (hh >> (64 - log2));
+    // the top log2 bits of the hash (log2 <= 30: they all sit in its upper word)
+    return exact ? (uint64_t)x0 : (uint64_t)((uint32_t)(hh >> 32) >> (32 - log2));
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -741,11 +742,14 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
                 const int jm = min((int)(my & 255u), n - 1);
                 const uint64_t hc = w.h ^ zk[jm];
                 const uint32_t x0 = w.x0 ^ (jm < 32 ? 1u << (jm & 31) : 0u);
-                uint64_t got = 0;
-                if (w.lane < PW && my != 0xFFFFFFFFu)
-                    got = T[slot_of(hc, x0, exact, tlog2)];
-                const bool fresh = (w.lane < PW) && (my != 0xFFFFFFFFu) && (got != (hc | 1ull));
-                const uint64_t okmask = ballot(fresh);
+                // every lane loads (lanes from PW on repeat lane 0's probe, an empty candidate reads
+                // the slot of flip n - 1: all addresses are valid); only the candidates' lanes count
+                const uint64_t got = T[slot_of(hc, x0, exact, tlog2)];
+                uint64_t pmask = 0;
+#pragma unroll
+                for (int i = 0; i < PW; i++)
+                    pmask |= cand[i] != 0xFFFFFFFFu ? 1ull << i : 0ull;
+                const uint64_t okmask = ballot(got != (hc | 1ull)) & pmask;
                 if (okmask != 0ull) {
                     const int first = __builtin_ctzll(okmask);
                     uint32_t pick = cand[0];
