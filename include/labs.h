@@ -262,7 +262,8 @@ int labs_general_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, labs_walk
 typedef struct labs_walk_plan labs_walk_plan;
 
 /* Allocates device state for n_walks walks (visited tables: n_walks * 2^table_log2 * 8 bytes;
- * LABS_ENOMEM if it does not fit), uploads cfg and resolves the options (opts may be NULL =
+ * LABS_ENOMEM if it does not fit, or if the tables, trace records or score entries of the batch
+ * add up to more than 2^40 entries), uploads cfg and resolves the options (opts may be NULL =
  * all auto).  The plan owns its device memory until labs_walk_plan_destroy. */
 int labs_walk_plan_create(int32_t n_walks, const labs_walk_cfg *cfg, const labs_plan_opts *opts,
                           labs_walk_plan **plan);

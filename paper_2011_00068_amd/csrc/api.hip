@@ -479,6 +479,12 @@ extern "C" int labs_walk_plan_create(int32_t n_walks, const labs_walk_cfg *cfg, 
         w.status = kFresh;
         p->pristine[(size_t)i] = w;
         p->max_steps = std::max(p->max_steps, c.steps);
+        // (each term is below 2^48, so the running sums cannot overflow before this test)
+        if (p->trace_records > ((int64_t)1 << 40) || p->score_entries > ((int64_t)1 << 40) ||
+            table_words > ((int64_t)1 << 40)) {
+            plan_free(p);
+            return fail(LABS_ENOMEM, "walk %d: trace, score or table buffers above 2^40 entries", i);
+        }
     }
     rc = resolve_opts(p, opts);
     if (rc) {
@@ -690,6 +696,9 @@ static int batch_sync(bool general, int32_t n_walks, const labs_walk_cfg *cfg, i
         w.hit_step = -1;
         w.watch_step = -1;
         w.status = kFresh;
+        if (trace_records > ((int64_t)1 << 40) || score_entries > ((int64_t)1 << 40) ||
+            table_words > ((int64_t)1 << 40))
+            return fail(LABS_ENOMEM, "walk %d: trace, score or table buffers above 2^40 entries", i);
     }
     // one launch per kernel shape, over the walks of that shape
     auto shape_of = [&](int L) { return general ? general_shape_for_length(L) : shape_for_length(L); };

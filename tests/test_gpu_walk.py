@@ -234,6 +234,14 @@ def test_walk_batch_entry_point(labs):
         assert_same(res[w], oracle_walk(c, trace=True), w)
 
 
+def test_walk_rejects_oversized_buffers(labs):
+    # two traced walks of 2^40 steps ask for 2^41 trace records: refused before any allocation
+    cfgs = [labs.make_cfg(31, SEED, w, steps=1 << 40, trace=True) for w in range(2)]
+    with pytest.raises(labs.LabsError) as e:
+        labs.WalkPlan(cfgs)
+    assert e.value.code == labs.LABS_ENOMEM
+
+
 def test_walk_rejects_bad_config(labs):
     for bad in (dict(L=4), dict(L=1), dict(L=385), dict(table_log2=0), dict(table_log2=31), dict(steps=-1)):
         kw = dict(L=31, seed=1, walk_id=0, steps=10, table_log2=16)
