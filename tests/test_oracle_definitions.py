@@ -10,8 +10,9 @@ import pytest
 from oracle import oracle as o
 from tests import table1
 
-# Table 1 rows whose printed F no integer ISL of the printed sequence reproduces (see the design doc,
-# "readings"): the computed ISL is asserted instead.
+# Table 1 rows whose printed F the printed sequence does not reproduce (for L = 281 no integer ISL
+# gives the printed F; for L = 283 the sequence's own ISL gives another F): the ISL computed from
+# the printed sequence is asserted instead.
 TABLE1_ERRATA_ISL = {281: 4604, 283: 4837}
 
 

@@ -1,5 +1,6 @@
 """Internal-consistency pins of the oracle's walk (the paper leaves the tie-break, the visited
-table, the random start and the restart rule open): the fast walk equals the walk
+table, the random start and the restart rule open; the oracle fixes them as its module header
+states): the fast walk equals the walk
 that recomputes every score from scratch, the bounded table equals an exact visited set while
 nothing is evicted, the walk is self-avoiding, and restarts / targets behave as specified."""
 import numpy as np
