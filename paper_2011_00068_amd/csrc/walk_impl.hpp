@@ -535,8 +535,7 @@ __device__ inline void clear_table(uint64_t *T, int log2)
 
 __device__ inline uint64_t slot_of(uint64_t hh, uint32_t x0, bool exact, int log2)
 {
-    // the top log2 bits of the hash (log2 <= 30: they all sit in its upper word)
-    return exact ? (uint64_t)x0 : (uint64_t)((uint32_t)(hh >> 32) >> (32 - log2));
+    return exact ? (uint64_t)x0 : (hh >> (64 - log2));
 }
 
 // ---------------------------------------------------------------------------------------------
