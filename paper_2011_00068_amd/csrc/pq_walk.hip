@@ -386,6 +386,12 @@ __device__ __forceinline__ void run_pq(WalkState *__restrict__ wsp, uint64_t *__
                 e_x[i] = readlane(pq.x[i], 0);
             pq.pop_front(w.lane);
             q--;
+            // an entry offered in this iteration was probed then, and the table has not changed
+            // since: it is unvisited without a second look
+            if (e_gen == t) {
+                found = true;
+                break;
+            }
             uint64_t got = 0;
             if (w.lane == 0)
                 got = T[slot_of(e_h, e_x[0], exact, tlog2)];
