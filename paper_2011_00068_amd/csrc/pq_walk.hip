@@ -30,7 +30,7 @@ namespace liblabs {
 namespace {
 
 constexpr int kPqProbe = 4;     // visited-table probes issued together
-constexpr int kPqNearFlips = 6; // an older queue entry this close is reached by single flips
+constexpr int kPqNearFlips = 24; // an older queue entry this close is reached by single flips (cheaper than a rebuild)
 
 __device__ __forceinline__ bool readlane_b(bool v, int l)
 {
