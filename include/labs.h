@@ -253,6 +253,14 @@ int labs_pq_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, const labs_pq_
  * ------------------------------------------------------------------------------------------- */
 #define LABS_GENERAL_L_MAX 192
 
+/* ISL of every one-symbol flip of a batch of general sequences (Eq. (1)-(2), all shifts):
+ * x_dev: device, count * LABS_X_WORDS uint32 (bit j of state r = b_j, j < L; higher bits ignored);
+ * scores_dev: device, count * L int32; scores_dev[r*L + j] = ISL of state r with s_j negated.
+ * 3 <= L <= LABS_GENERAL_L_MAX.  Asynchronous on stream; LABS_EINVAL for a bad L, count < 0 or
+ * NULL buffers with count > 0. */
+int labs_general_flip_scores_dev(int32_t L, int32_t count, const uint32_t *x_dev, int32_t *scores_dev,
+                                 void *stream);
+
 /* Runs n_walks general walks to completion (one launch per kernel shape; steps <= 2^30 per walk);
  * arguments and results as labs_pq_walk_batch (scores: steps * L int32 per walk with
  * LABS_TRACE_SCORES).  Synchronous on stream; allocates and frees its device state. */

@@ -46,7 +46,7 @@ EXPORTS = [
     "labs_flip_scores_dev",
     "labs_walk_batch", "labs_walk_plan_create", "labs_walk_plan_run", "labs_walk_plan_results",
     "labs_walk_plan_get_opts", "labs_walk_plan_last_timing", "labs_walk_plan_destroy",
-    "labs_autotune", "labs_pq_walk_batch", "labs_general_walk_batch",
+    "labs_autotune", "labs_pq_walk_batch", "labs_general_walk_batch", "labs_general_flip_scores_dev",
     "labs_server_create", "labs_search_submit", "labs_search_poll", "labs_search_wait",
     "labs_search_cancel", "labs_server_stats", "labs_server_destroy",
 ]
@@ -201,6 +201,7 @@ def lib():
     L.labs_pq_walk_batch.argtypes = [i32, P(WalkCfg), P(PqOpts), P(WalkResult), vp, vp,
                                      P(ctypes.c_double), vp]
     L.labs_general_walk_batch.argtypes = [i32, P(WalkCfg), P(WalkResult), vp, vp, P(ctypes.c_double), vp]
+    L.labs_general_flip_scores_dev.argtypes = [i32, i32, vp, vp, vp]
     L.labs_server_create.argtypes = [P(ServerOpts), P(vp)]
     L.labs_search_submit.argtypes = [vp, P(SearchReq), P(u64)]
     L.labs_search_poll.argtypes = [vp, u64, P(SearchStatus)]
@@ -321,6 +322,17 @@ def flip_scores(L, xs, variant=VARIANT_BITSLICE, device="cuda"):
     out = torch.empty(len(xs), n, dtype=torch.int32, device=device)
     _check(lib().labs_flip_scores_dev(L, len(xs), _ptr(x_dev), _ptr(out), variant, _stream()),
            "labs_flip_scores_dev")
+    return out
+
+
+def general_flip_scores(L, xs, device="cuda"):
+    """Scores of every one-symbol flip of each general sequence in xs (Python ints, bit j = b_j).
+    Returns int32 [count, L]."""
+    words = torch.tensor([x_words(x) for x in xs], dtype=torch.int64).to(torch.int32)
+    x_dev = words.to(device).contiguous()
+    out = torch.empty(len(xs), L, dtype=torch.int32, device=device)
+    _check(lib().labs_general_flip_scores_dev(L, len(xs), _ptr(x_dev), _ptr(out), _stream()),
+           "labs_general_flip_scores_dev")
     return out
 
 

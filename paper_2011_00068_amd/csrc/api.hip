@@ -807,6 +807,19 @@ extern "C" int labs_pq_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, con
                       stream);
 }
 
+extern "C" int labs_general_flip_scores_dev(int32_t L, int32_t count, const uint32_t *x_dev, int32_t *scores_dev,
+                                            void *stream)
+{
+    if (L < 3 || L > LABS_GENERAL_L_MAX || count < 0 || (count > 0 && (!x_dev || !scores_dev)))
+        return fail(LABS_EINVAL, "labs_general_flip_scores_dev: bad arguments (L = %d, count = %d)", L, count);
+    int rc = check_device();
+    if (rc)
+        return rc;
+    HIP_TRY(launch_general_flip_scores(L, count, x_dev, scores_dev, (hipStream_t)stream),
+            "labs_general_flip_scores_dev");
+    return LABS_OK;
+}
+
 extern "C" int labs_general_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, labs_walk_result *out,
                                        int32_t *trace, int32_t *scores, double *kernel_ms, void *stream)
 {

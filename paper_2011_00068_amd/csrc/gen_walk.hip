@@ -334,7 +334,60 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8)))
     run_walk<W, 2>(&states[order[idx]], tables, trace, scores, 0, &lds, zk);
 }
 
+// ISL_j of every flip of a batch of states (free bits, kXWords words per state), out[r * L + j]
+template <int SHAPE>
+__global__ void __launch_bounds__(64) k_general_flip_scores(int L, int count, const uint32_t *__restrict__ xs,
+                                                            int32_t *__restrict__ out)
+{
+    __shared__ uint64_t zk[kNMax];
+    __shared__ WaveLdsGenMfma lds;
+    fill_zobrist(zk);
+    const int r = (int)blockIdx.x;
+    if (r >= count)
+        return;
+    using W = GenMfmaWalker<GenShape<SHAPE>::G, GenShape<SHAPE>::KB>;
+    W w;
+    w.lane = lane_id();
+    w.set_length(L);
+    w.lds = &lds;
+    w.zk = zk;
+    w.init_lanes(w.lane);
+#pragma unroll
+    for (int i = 0; i < kXWords; i++)
+        w.x[i] = xs[(int64_t)r * kXWords + i];
+    w.rebuild();
+    w.prepare();
+    int32_t isl_j[W::kG];
+    w.score(isl_j);
+#pragma unroll
+    for (int g = 0; g < W::kG; g++) {
+        const int j = w.flip(g);
+        if (j < w.n)
+            out[(int64_t)r * w.n + j] = isl_j[g];
+    }
+}
+
 } // namespace
+
+hipError_t launch_general_flip_scores(int L, int count, const uint32_t *x, int32_t *scores, hipStream_t stream)
+{
+    if (count <= 0)
+        return hipSuccess;
+    void (*k)(int, int, const uint32_t *, int32_t *) = nullptr;
+    switch (general_shape_for_length(L)) {
+    case 0: k = k_general_flip_scores<0>; break;
+    case 1: k = k_general_flip_scores<1>; break;
+    case 2: k = k_general_flip_scores<2>; break;
+    case 3: k = k_general_flip_scores<3>; break;
+    case 4: k = k_general_flip_scores<4>; break;
+    case 5: k = k_general_flip_scores<5>; break;
+    case 6: k = k_general_flip_scores<6>; break;
+    case 7: k = k_general_flip_scores<7>; break;
+    default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k, dim3(count), dim3(64), 0, stream, L, count, x, scores);
+    return hipGetLastError();
+}
 
 int general_shape_for_length(int L)
 {

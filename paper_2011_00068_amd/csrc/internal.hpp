@@ -84,6 +84,7 @@ int lds_probe_threads();
 double lds_probe_bytes(int bytes_per_lane, int blocks, int rounds);
 hipError_t launch_lds_read_probe(int bytes_per_lane, int blocks, int rounds, uint32_t *out, hipStream_t stream);
 int general_shape_for_length(int L);
+hipError_t launch_general_flip_scores(int L, int count, const uint32_t *x, int32_t *scores, hipStream_t stream);
 constexpr int kMfmaLMax = 383;     // the matrix-core scoring covers every walk length
 constexpr int kMfmaAutoLMin = 129; // below it the bit-sliced scoring is as fast (measured)
 hipError_t launch_flip_scores_mfma(int L, int count, const uint32_t *x, int32_t *scores, hipStream_t stream);

@@ -64,6 +64,39 @@ def test_targets_traps_exact_table(labs):
     assert got[1]["best_isl"] == 6 and got[1]["hit_step"] > 0
 
 
+def _seq(L, x):
+    return np.array([-1 if (x >> j) & 1 else 1 for j in range(L)], dtype=np.int8)
+
+
+def test_flip_scores_every_length(labs):
+    # every L in [3, 192]: random states, all +1, all -1 and the alternating sequence (whose
+    # correlations |C_k| = L - k leave the int8 range from L = 129 on: the two-pass product)
+    for L in range(3, 193):
+        rng = np.random.default_rng(L)
+        alt = sum(1 << j for j in range(1, L, 2))
+        xs = [int(rng.integers(0, 1 << 62)) | (int(rng.integers(0, 1 << 62)) << 62) |
+              (int(rng.integers(0, 1 << 62)) << 124) for _ in range(2)]
+        xs = [x & ((1 << L) - 1) for x in xs] + [0, (1 << L) - 1, alt]
+        got = labs.general_flip_scores(L, xs).cpu().numpy()
+        for i, x in enumerate(xs):
+            s = _seq(L, x)
+            C = np.array([0] + [int(np.dot(s[: L - k].astype(np.int64), s[k:])) for k in range(1, L)])
+            want = [o.flip_isl_general(s, j, C) for j in range(L)]
+            assert np.array_equal(got[i], want), (L, i)
+    # the plain definition on a few states
+    for L in (3, 64, 65, 128, 129, 192):
+        x = (1 << L) - 1
+        got = labs.general_flip_scores(L, [x]).cpu().numpy()[0]
+        assert all(got[j] == o.flip_isl_general(_seq(L, x), j) for j in range(L)), L
+
+
+def test_flip_scores_rejects_bad_lengths(labs):
+    for L in (2, 193):
+        with pytest.raises(labs.LabsError) as e:
+            labs.general_flip_scores(L, [1])
+        assert e.value.code == labs.LABS_EINVAL
+
+
 def test_targets_traps_exact_table_untraced(labs):
     # the same kinds of walks without traces (the step loop built without trace tests, for tables
     # addressed by the free bits and by the hash)
