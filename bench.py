@@ -167,12 +167,13 @@ def serving(labs, rate=20.0, n_requests=100, seed=SEED):
 
 
 def uneven_batch(labs):
-    """Every odd L in [201, 303] x 64 walks x 10^6 steps in one launch (mixed shapes)."""
+    """Every odd L in [201, 303] x 64 walks x 10^6 steps in one persistent launch of mixed shapes,
+    replayed from a captured hipGraph."""
     import torch
 
     cfg = [labs.make_cfg(L, SEED, w, steps=10 ** 6, table_log2=TABLE_LOG2) for L in range(201, 304, 2)
            for w in range(64)]
-    plan = labs.WalkPlan(cfg)
+    plan = labs.WalkPlan(cfg, use_graph=True)
     plan.run()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -182,7 +183,7 @@ def uneven_batch(labs):
     res = plan.results()
     plan.close()
     flips = sum(r["flip_evals"] for r in res)
-    return {"walks": len(cfg), "steps_per_walk": 10 ** 6, "launches": launches, "kernel_ms": ms,
+    return {"walks": len(cfg), "steps_per_walk": 10 ** 6, "launches": launches, "hipgraph": True, "kernel_ms": ms,
             "flip_evals_per_s": flips / wall,
             "alg_ops_frac_of_valu_peak": sum(r["flip_evals"] * 3 * (c.L - 1) // 2 for r, c in zip(res, cfg))
             / (ms / 1000.0) / (VALU_PEAK_TOPS * 1e12)}
