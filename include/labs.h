@@ -124,8 +124,9 @@ int labs_enum_skew_min(int32_t L, uint64_t r_begin, uint64_t r_end, labs_enum_mi
 /* Scores of every flip of `count` skew-symmetric states of odd length L, 3 <= L <=
  * LABS_WALK_L_MAX: scores_dev[r*n + j] = ISL of state r with flip j applied, computed from the
  * state's correlation table as the walk does.  x_dev: device, count * LABS_X_WORDS uint32
- * (bits at j >= n must be 0, else LABS_EINVAL is not detected: they are ignored).  variant:
- * LABS_VARIANT_* below.  Asynchronous on stream. */
+ * (bits at j >= n are ignored).  variant: LABS_VARIANT_* below (AUTO = BITSLICE here).
+ * Asynchronous on stream; LABS_EINVAL for a bad L, count < 0, NULL buffers with count > 0, an
+ * unknown variant, or LABS_VARIANT_MFMA beyond its range. */
 int labs_flip_scores_dev(int32_t L, int32_t count, const uint32_t *x_dev, int32_t *scores_dev,
                          int32_t variant, void *stream);
 
@@ -186,7 +187,7 @@ typedef struct labs_walk_result {
 #define LABS_VARIANT_BITSLICE 1 /* bit-sliced correlation table, popcount scoring */
 #define LABS_VARIANT_DIRECT 2   /* int8 sequence + int32 table in LDS, direct sum of squares */
 #define LABS_VARIANT_MFMA 3     /* the correlation sums of every flip as int8 matrix-core tiles:
-                                   one per step for L <= 255, two beyond (every L <= 383) */
+                                   one tile per step for L <= 255, two beyond (every L <= 383) */
 
 typedef struct labs_plan_opts {
     int32_t variant;          /* LABS_VARIANT_* */
