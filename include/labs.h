@@ -124,7 +124,8 @@ int labs_enum_skew_min(int32_t L, uint64_t r_begin, uint64_t r_end, labs_enum_mi
 /* Scores of every flip of `count` skew-symmetric states of odd length L, 3 <= L <=
  * LABS_WALK_L_MAX: scores_dev[r*n + j] = ISL of state r with flip j applied, computed from the
  * state's correlation table as the walk does.  x_dev: device, count * LABS_X_WORDS uint32
- * (bits at j >= n are ignored).  variant: LABS_VARIANT_* below (AUTO = BITSLICE here).
+ * (bits at j >= n must be 0; not checked).  variant: LABS_VARIANT_* below (AUTO = BITSLICE
+ * here).
  * Asynchronous on stream; LABS_EINVAL for a bad L, count < 0, NULL buffers with count > 0, an
  * unknown variant, or LABS_VARIANT_MFMA beyond its range. */
 int labs_flip_scores_dev(int32_t L, int32_t count, const uint32_t *x_dev, int32_t *scores_dev,
@@ -255,7 +256,8 @@ int labs_pq_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, const labs_pq_
 #define LABS_GENERAL_L_MAX 192
 
 /* ISL of every one-symbol flip of a batch of general sequences (Eq. (1)-(2), all shifts):
- * x_dev: device, count * LABS_X_WORDS uint32 (bit j of state r = b_j, j < L; higher bits ignored);
+ * x_dev: device, count * LABS_X_WORDS uint32 (bit j of state r = b_j, j < L; higher bits must be 0,
+ * not checked);
  * scores_dev: device, count * L int32; scores_dev[r*L + j] = ISL of state r with s_j negated.
  * 3 <= L <= LABS_GENERAL_L_MAX.  Asynchronous on stream; LABS_EINVAL for a bad L, count < 0 or
  * NULL buffers with count > 0. */
