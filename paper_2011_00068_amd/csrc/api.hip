@@ -915,18 +915,12 @@ static int resolve_opts(labs_walk_plan *p, const labs_plan_opts *in)
     // shapes present
     int shape = -2;
     int maxL = 0, minL = 1 << 30;
-    bool same_steps = true;
     for (const labs_walk_cfg &c : p->cfg) {
         const int s = shape_for_length(c.L);
         shape = (shape == -2 || shape == s) ? s : -1;
         maxL = std::max(maxL, c.L);
         minL = std::min(minL, c.L);
-        same_steps = same_steps && c.steps == p->cfg[0].steps;
     }
-    // walks of one shape and one budget cost about the same: the hardware's own scheduling of one
-    // wave per walk beats resident waves pulling walks from a counter (measured at the L = 255
-    // headline, 3 %); uneven batches keep the pulling grid, costliest walks first
-    const bool uniform = shape >= 0 && same_steps;
     labs_plan_opts tuned{};
     const bool have = cache_lookup(maxL, &tuned);
     // untuned default: the matrix-core scoring where it was measured faster (L >= 129),
@@ -938,9 +932,8 @@ static int resolve_opts(labs_walk_plan *p, const labs_plan_opts *in)
         return fail(LABS_EINVAL, "unknown variant %d", o.variant);
     if (o.variant == LABS_VARIANT_MFMA && maxL > kMfmaLMax)
         return fail(LABS_EINVAL, "the matrix-core variant needs L <= %d (longest walk: %d)", kMfmaLMax, maxL);
-    if (o.waves_per_block == 0) // uneven matrix-core batches: two walks per workgroup share the
-        // Zobrist keys and keep the big LDS layout within the waves per SIMD the kernel targets
-        o.waves_per_block = have ? tuned.waves_per_block : (o.variant == LABS_VARIANT_MFMA && !uniform ? 2 : 1);
+    if (o.waves_per_block == 0)
+        o.waves_per_block = have ? tuned.waves_per_block : 1;
     if (o.waves_per_block != 1 && o.waves_per_block != 2 && o.waves_per_block != 4 && o.waves_per_block != 8)
         return fail(LABS_EINVAL, "waves_per_block = %d must be 0, 1, 2, 4 or 8", o.waves_per_block);
     if (o.probe_width == 0) // measured: two probes in flight pay off for the matrix-core walker only
@@ -954,8 +947,11 @@ static int resolve_opts(labs_walk_plan *p, const labs_plan_opts *in)
     if (o.steps_per_launch == 0)
         o.steps_per_launch = std::max<int64_t>(p->max_steps, 1);
     o.steps_per_launch = std::min<int64_t>(o.steps_per_launch, (int64_t)1 << 30); // kernel limit
+    // one wave per walk, the hardware dispatching workgroups as others finish (walks in the
+    // costliest-first order), measured 1-3 % faster than resident waves pulling walks from a
+    // counter for the matrix-core walker, at the L = 255 headline and on the uneven batch
     if (o.persistent == 0)
-        o.persistent = have ? tuned.persistent : (o.variant == LABS_VARIANT_MFMA && !uniform ? 2 : 1);
+        o.persistent = have ? tuned.persistent : 1;
     if (o.persistent != 1 && o.persistent != 2)
         return fail(LABS_EINVAL, "persistent = %d must be 0, 1 or 2", o.persistent);
     persistent = o.persistent == 2;
