@@ -167,7 +167,7 @@ def serving(labs, rate=20.0, n_requests=100, seed=SEED):
 
 
 def uneven_batch(labs):
-    """Every odd L in [201, 303] x 64 walks x 10^6 steps in one persistent launch of mixed shapes,
+    """Every odd L in [201, 303] x 64 walks x 10^6 steps in one launch of mixed shapes,
     replayed from a captured hipGraph."""
     import torch
 
