@@ -137,9 +137,21 @@ __global__ void __launch_bounds__(kEnumBlock) k_enum_min(int L, uint64_t r_begin
 
     uint32_t best = 0xFFFFFFFFu, cnt = 0;
     uint64_t first = ~0ull;
+    // Pruning bound (wave-uniform): the lowest ISL any lane of the wave has found, and what this
+    // block slot holds from earlier launches of the same enumeration.  Every C_k^2 >= 0, so a
+    // partial sum above the bound is above the minimum: once every sequence of the wave's pass is
+    // above it, the pass stops (a sequence at the minimum is never cut, so the minimum, its
+    // multiplicity and its lowest argument are unchanged).
+    const uint32_t bound0 = part[blockIdx.x].min_isl;
     const uint64_t n_pass = (r_count + kEnumB - 1) / kEnumB;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_pass; g += stride) {
+    // the loop runs per wave (every lane stays active for the wave-wide reductions); lanes past
+    // the last pass compute a sequence that is never recorded or counted as live
+    const uint64_t wave_base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(uint32_t)(kWave - 1));
+    for (uint64_t g0 = wave_base; g0 < n_pass; g0 += stride) {
+        const uint64_t g = g0 + lane_id();
+        const bool valid = g < n_pass;
+        const uint32_t bound = min(bound0, wave_min_u32(best));
         uint32_t w[kEnumB][NW + 1];
         uint32_t isl[kEnumB];
 #pragma unroll
@@ -148,8 +160,9 @@ __global__ void __launch_bounds__(kEnumBlock) k_enum_min(int L, uint64_t r_begin
             expand<NW>(r << 2, sh, hi_mask, alt, w[u]);
             isl[u] = 0;
         }
+        bool cut = false;
 #pragma unroll
-        for (int q = 0; q < NW; q++) {
+        for (int q = 0; q < NW && !cut; q++) {
 #pragma unroll 1
             for (int b = (q == 0 ? 2 : 0); b < 32; b += 2) {
                 const int k = 32 * q + b;
@@ -172,8 +185,19 @@ __global__ void __launch_bounds__(kEnumBlock) k_enum_min(int L, uint64_t r_begin
                         e = bcnt_acc((w[u][i] ^ funnel(w[u][i + q + 1], w[u][i + q], b)) & m[i], e);
                     isl[u] = sq_acc(e, isl[u]);
                 }
+                bool live = false;
+#pragma unroll
+                for (int u = 0; u < kEnumB; u++)
+                    live = live || isl[u] <= bound;
+                live = live && valid;
+                if (ballot(live) == 0ull) {
+                    cut = true;
+                    break;
+                }
             }
         }
+        if (cut)
+            continue;
         uint32_t lo = isl[0];
 #pragma unroll
         for (int u = 1; u < kEnumB; u++)
