@@ -19,7 +19,7 @@ namespace liblabs {
 namespace {
 
 constexpr int kEnumBlock = 256;
-constexpr int kEnumB = 4;
+constexpr int kEnumB = 8;
 
 // x -> the L-bit sequence (bit 1 = symbol -1) in w[0..NW-1], w[NW] = 0: bits 0..c are x, bit
 // c + i is bit c - i of x flipped for odd i (Eq. (4)).  hi_mask / alt: bits c+1..2c, and the odd
