@@ -29,7 +29,11 @@
  * consistency (incremental walk == recomputing walk, bounded table == exact set before any
  * eviction, no revisits, best == first minimum of the trajectory).  So are the queue order,
  * capacity and discard rules of ref_pq_walk: it is checked against ref_walk (capacity 1) and
- * against an independent Python statement of the same reading.
+ * against an independent Python statement of the same reading; and so are the scan order, the
+ * perturbation draw and its size of ref_fi_walk: it is checked against the plain definition of
+ * every flip score, an independent numpy statement of the same reading, its move and local-minimum
+ * rules, the negation symmetry (a perturbation of every symbol keeps the ISL) and the uniformity
+ * of the draw.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -553,14 +557,25 @@ int ref_walk(const ref_walk_cfg *cfg, ref_walk_result *res, int32_t *trace, int3
         }                                                                                      \
     } while (0)
 
+/* Every state the walk occupies counts for best, hit and watch, start states included: the
+ * initial state (Algorithm 1 initialises the best from it) and every restart state (a restart is
+ * that same initialisation, Section 2).  t = the step after which the state is occupied. */
+#define NOTE_STATE(t_)                                                                         \
+    do {                                                                                       \
+        if (isl < res->best_isl) {                                                             \
+            res->best_isl = isl;                                                               \
+            res->best_step = (t_);                                                             \
+            to_u32_words(x, nwords, res->best_bits);                                           \
+        }                                                                                      \
+        if (cfg->target_isl >= 0 && res->hit_step < 0 && isl <= cfg->target_isl)             \
+            res->hit_step = (t_);                                                              \
+        if (cfg->watch_isl >= 0 && res->watch_step < 0 && isl <= cfg->watch_isl)             \
+            res->watch_step = (t_);                                                            \
+    } while (0)
+
     START_STATE();
-    res->best_isl = isl;
-    res->best_step = 0;
-    to_u32_words(x, nwords, res->best_bits);
-    if (cfg->target_isl >= 0 && isl <= cfg->target_isl)
-        res->hit_step = 0;
-    if (cfg->watch_isl >= 0 && isl <= cfg->watch_isl)
-        res->watch_step = 0;
+    res->best_isl = INT64_MAX;
+    NOTE_STATE(0);
 
     int64_t t = 0, flips = 0;
     while (t < cfg->steps && !(cfg->target_isl >= 0 && res->hit_step >= 0)) {
@@ -590,7 +605,7 @@ int ref_walk(const ref_walk_cfg *cfg, ref_walk_result *res, int32_t *trace, int3
         }
 
         if (jb < 0) {
-            /* every neighbour visited: restart from a fresh start state */
+            /* every neighbour visited: restart from a fresh start state (the step counts) */
             res->traps++;
             res->restarts++;
             restart++;
@@ -600,6 +615,7 @@ int ref_walk(const ref_walk_cfg *cfg, ref_walk_result *res, int32_t *trace, int3
                 trace[2 * t - 2] = -1;
                 trace[2 * t - 1] = (int32_t)isl;
             }
+            NOTE_STATE(t);
             continue;
         }
 
@@ -626,23 +642,17 @@ int ref_walk(const ref_walk_cfg *cfg, ref_walk_result *res, int32_t *trace, int3
             trace[2 * t - 2] = jb;
             trace[2 * t - 1] = (int32_t)isl;
         }
-        if (isl < res->best_isl) {
-            res->best_isl = isl;
-            res->best_step = t;
-            to_u32_words(x, nwords, res->best_bits);
-        }
-        if (cfg->target_isl >= 0 && res->hit_step < 0 && isl <= cfg->target_isl)
-            res->hit_step = t;
-        if (cfg->watch_isl >= 0 && res->watch_step < 0 && isl <= cfg->watch_isl)
-            res->watch_step = t;
+        NOTE_STATE(t);
         /* periodic restart (lssOrel-style, Section 2), only if the walk goes on */
         if (cfg->restart_period > 0 && t % cfg->restart_period == 0 && t < cfg->steps &&
             !(cfg->target_isl >= 0 && res->hit_step >= 0)) {
             res->restarts++;
             restart++;
             START_STATE();
+            NOTE_STATE(t);
         }
     }
+#undef NOTE_STATE
 #undef START_STATE
 
     res->steps_done = t;
@@ -750,8 +760,10 @@ int ref_enum_skew_min(int32_t L, uint64_t r_begin, uint64_t r_end, int64_t *min_
  *   - an empty queue (nothing left to take) restarts the search (a trap, counted like a
  *     restart); restarts clear HT, the second table and the queue.
  *   - best: strict improvement, checked when a neighbour is evaluated; best_step is the
- *     iteration count after the iteration that evaluated it.  hit_step / watch_step: the first
- *     iteration count after which the best ISL is <= target_isl / watch_isl (0 for the start).
+ *     iteration count after the iteration that evaluated it.  Start states count as well (the
+ *     initial one at 0, a restart state at the iteration count after which it is occupied, as
+ *     in ref_walk).  hit_step / watch_step: the first iteration count after which the best ISL
+ *     is <= target_isl / watch_isl (0 for the start).
  *   - flip_evals: n per iteration, less the neighbours skipped by the second table (a
  *     neighbour in HT counts, as in ref_walk).  A neighbour in HT is not recorded in the
  *     second table.
@@ -914,6 +926,12 @@ int ref_pq_walk(const ref_walk_cfg *cfg, int32_t capacity, int32_t nbr_log2, ref
             restart++;
             PQ_START();
             move = -1;
+            /* a restart state counts like the initial state (see ref_walk) */
+            if (isl < res->best_isl) {
+                res->best_isl = isl;
+                res->best_step = t + 1;
+                to_u32_words(x, nwords, res->best_bits);
+            }
         } else {
             move = (f.gen == t) ? f.j : -2;
             memcpy(x, f.x, sizeof x);
@@ -943,6 +961,15 @@ int ref_pq_walk(const ref_walk_cfg *cfg, int32_t capacity, int32_t nbr_log2, ref
             res->restarts++;
             restart++;
             PQ_START();
+            if (isl < res->best_isl) {
+                res->best_isl = isl;
+                res->best_step = t;
+                to_u32_words(x, nwords, res->best_bits);
+            }
+            if (cfg->target_isl >= 0 && res->hit_step < 0 && res->best_isl <= cfg->target_isl)
+                res->hit_step = t;
+            if (cfg->watch_isl >= 0 && res->watch_step < 0 && res->best_isl <= cfg->watch_isl)
+                res->watch_step = t;
         }
     }
 #undef PQ_START
@@ -959,4 +986,170 @@ int ref_pq_walk(const ref_walk_cfg *cfg, int32_t capacity, int32_t nbr_log2, ref
     free(B.T);
     free(N.T);
     return 0;
+}
+
+/* ------------------------------------------------------------------------------------------
+ * First-improvement search with perturbations: the method of Dimitrov et al. as Section 2
+ * describes it.  Like lssOrel it moves by single flips of the free symbols, but it moves at
+ * once to the first flip that improves the merit factor and starts a new scan from that
+ * sequence; when no flip improves it (a local minimum of the one-flip neighbourhood) it flips a
+ * few randomly chosen symbols and goes on from there.  Merit factors of flips come from the
+ * stored correlation values C_k (the one-dimensional structure Section 2 mentions).
+ * Readings of what the paper leaves open:
+ *   - scan order: flips j = 0 .. c in index order, from j = 0 again after every move; a flip
+ *     improves when its ISL is strictly lower than the current ISL.
+ *   - perturbation: P distinct free symbols (P is a parameter, 1 <= P <= min(n, 32)); the k-th
+ *     perturbation of the walk (k = 0, 1, ... counted over the whole walk, restarts included)
+ *     draws words u_i = sm64_at(sm64_at(sm64_at(seed, walk_id), 2^32 + k), i), i = 0, 1, ...,
+ *     takes j_i = floor((u_i >> 32) * n / 2^32) and skips indices already drawn, until P are
+ *     chosen (or 65536 words are drawn).  The perturbed sequence becomes the current one whatever
+ *     its ISL.
+ *   - one step = one scan: an improving move, or (no improving flip) a perturbation.  Function
+ *     evaluations (Section 3's unit): j + 1 for a move at flip j (flips 0 .. j were evaluated), n
+ *     + P for a perturbation (the n evaluated flips and the P flips applied).
+ *   - no visited table; restarts (restart_period), target and watch as in ref_walk; every
+ *     occupied state counts for best, hit and watch, start states included.
+ *   - results as ref_walk, with traps = the number of perturbations; trace per step (j of the
+ *     move, or -1 for a perturbation; ISL after the step); score trace: the ISL of every flip of
+ *     the state the step started from.
+ * ---------------------------------------------------------------------------------------- */
+
+/* Free symbols flipped by perturbation k of a walk (the draw stated above), in draw order; the
+ * number found (P, unless 65536 draws did not find P distinct symbols, which a uniform draw of P
+ * <= n <= 192 symbols makes vanishingly unlikely; then the ones found). */
+int32_t ref_perturb_indices(int32_t n, uint64_t seed, uint32_t walk_id, uint64_t k, int32_t P, int32_t *out)
+{
+    const uint64_t kw = ref_sm64_at(seed, walk_id);
+    const uint64_t kp = ref_sm64_at(kw, ((uint64_t)1 << 32) + k);
+    int32_t got = 0;
+    for (uint64_t i = 0; got < P && i < 65536; i++) {
+        const uint64_t u = ref_sm64_at(kp, i);
+        const int32_t j = (int32_t)(((u >> 32) * (uint64_t)n) >> 32);
+        int dup = 0;
+        for (int32_t q = 0; q < got; q++)
+            if (out[q] == j)
+                dup = 1;
+        if (!dup)
+            out[got++] = j;
+    }
+    return got;
+}
+
+int ref_fi_walk(const ref_walk_cfg *cfg, int32_t perturb, ref_walk_result *res, int32_t *trace,
+                int32_t *score_trace)
+{
+    const int32_t L = cfg->L;
+    if (L < 3 || (L % 2) == 0 || cfg->steps < 0)
+        return -1;
+    const int32_t n = (L + 1) / 2, c = n - 1;
+    const int32_t nwords = (n + 63) / 64;
+    if (nwords > ORACLE_MAX_WORDS || perturb < 1 || perturb > n || perturb > 32)
+        return -1;
+    const int brute = (cfg->flags & ORACLE_BRUTE) != 0;
+
+    int8_t *s = (int8_t *)malloc((size_t)L);
+    int64_t *C = (int64_t *)malloc(sizeof(int64_t) * (size_t)L);
+    int64_t *score = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    uint64_t x[ORACLE_MAX_WORDS];
+    int32_t pick[32];
+    memset(x, 0, sizeof x);
+    int64_t isl = 0;
+    uint32_t restart = 0;
+    uint64_t kpert = 0;
+
+    memset(res, 0, sizeof *res);
+    res->hit_step = -1;
+    res->watch_step = -1;
+    res->best_isl = INT64_MAX;
+
+#define FI_START()                                                                             \
+    do {                                                                                       \
+        ref_start_bits(L, cfg->seed, cfg->walk_id, restart, x, nwords);                        \
+        ref_skew_expand(L, x, s);                                                              \
+        isl = ref_isl(L, s);                                                                   \
+    } while (0)
+#define FI_NOTE(t_)                                                                            \
+    do {                                                                                       \
+        if (isl < res->best_isl) {                                                             \
+            res->best_isl = isl;                                                               \
+            res->best_step = (t_);                                                             \
+            to_u32_words(x, nwords, res->best_bits);                                           \
+        }                                                                                      \
+        if (cfg->target_isl >= 0 && res->hit_step < 0 && isl <= cfg->target_isl)             \
+            res->hit_step = (t_);                                                              \
+        if (cfg->watch_isl >= 0 && res->watch_step < 0 && isl <= cfg->watch_isl)             \
+            res->watch_step = (t_);                                                            \
+    } while (0)
+/* negate free symbol j (and its mirror unless j is the centre) */
+#define FI_FLIP(j_)                                                                            \
+    do {                                                                                       \
+        s[(j_)] = (int8_t)(-s[(j_)]);                                                          \
+        if ((j_) != c)                                                                         \
+            s[L - 1 - (j_)] = (int8_t)(-s[L - 1 - (j_)]);                                      \
+        x[(j_) / 64] ^= (uint64_t)1 << ((j_) % 64);                                            \
+    } while (0)
+
+    FI_START();
+    FI_NOTE(0);
+    int64_t t = 0, flips = 0;
+    int rc = 0;
+    while (t < cfg->steps && !(cfg->target_isl >= 0 && res->hit_step >= 0)) {
+        ref_corr(L, s, C);
+        for (int32_t j = 0; j < n; j++)
+            score[j] = brute ? ref_flip_isl_brute(L, s, j) : ref_flip_isl_incr(L, s, C, j);
+        if (score_trace)
+            for (int32_t j = 0; j < n; j++)
+                score_trace[t * n + j] = (int32_t)score[j];
+        /* the scan: the first flip in index order that improves the current ISL */
+        int32_t jb = -1;
+        for (int32_t j = 0; j < n && jb < 0; j++)
+            if (score[j] < isl)
+                jb = j;
+        int32_t move;
+        if (jb >= 0) {
+            FI_FLIP(jb);
+            flips += jb + 1;
+            isl = ref_isl(L, s);
+            if (isl != score[jb]) {
+                rc = -2;
+                break;
+            }
+            move = jb;
+        } else {
+            /* a local minimum: perturb P randomly chosen free symbols */
+            const int32_t np = ref_perturb_indices(n, cfg->seed, cfg->walk_id, kpert, perturb, pick);
+            kpert++;
+            for (int32_t q = 0; q < np; q++)
+                FI_FLIP(pick[q]);
+            flips += n + np;
+            isl = ref_isl(L, s);
+            res->traps++;
+            move = -1;
+        }
+        t++;
+        if (trace) {
+            trace[2 * t - 2] = move;
+            trace[2 * t - 1] = (int32_t)isl;
+        }
+        FI_NOTE(t);
+        if (cfg->restart_period > 0 && t % cfg->restart_period == 0 && t < cfg->steps &&
+            !(cfg->target_isl >= 0 && res->hit_step >= 0)) {
+            res->restarts++;
+            restart++;
+            FI_START();
+            FI_NOTE(t);
+        }
+    }
+#undef FI_FLIP
+#undef FI_NOTE
+#undef FI_START
+
+    res->steps_done = t;
+    res->flip_evals = flips;
+    res->final_isl = isl;
+    to_u32_words(x, nwords, res->final_bits);
+    free(s);
+    free(C);
+    free(score);
+    return rc;
 }

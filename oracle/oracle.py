@@ -76,6 +76,11 @@ def lib():
     L.ref_start_bits_general.argtypes = [
         ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, u64p, ctypes.c_int32
     ]
+    L.ref_fi_walk.argtypes = [ctypes.POINTER(WalkCfg), ctypes.c_int32, ctypes.POINTER(WalkResult), i32p, i32p]
+    L.ref_fi_walk.restype = ctypes.c_int
+    L.ref_perturb_indices.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
+                                      ctypes.c_int32, i32p]
+    L.ref_perturb_indices.restype = ctypes.c_int32
     L.ref_enum_skew.argtypes = [ctypes.c_int32, i64p]
     L.ref_enum_skew.restype = ctypes.c_int
     L.ref_enum_skew_min.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64, i64p, u64p, u64p]
@@ -250,11 +255,12 @@ def zobrist(j: int) -> int:
 
 def walk(L, seed, walk_id=0, steps=1000, table_log2=16, restart_period=0, target_isl=-1,
          watch_isl=-1, brute=False, ideal=False, trace=False, score_trace=False, pq_capacity=0,
-         nbr_table_log2=0, general=False):
+         nbr_table_log2=0, general=False, fi_perturb=0):
     """Runs one walk; returns a dict of results (+ 'trace' (steps,2) / 'scores' (steps,n)).
     pq_capacity > 0 runs the best-first search with a queue of that capacity instead (and
     nbr_table_log2 > 0 adds the second table of evaluated neighbours).  general=True walks over
-    general sequences (all L symbols free)."""
+    general sequences (all L symbols free).  fi_perturb > 0 runs the first-improvement search
+    with perturbations of that many symbols instead (traps = perturbations)."""
     n = L if general else (L + 1) // 2
     cfg = WalkCfg(L, table_log2, seed & 0xFFFFFFFFFFFFFFFF, walk_id,
                   (BRUTE if brute else 0) | (IDEAL if ideal else 0) | (GENERAL if general else 0),
@@ -265,7 +271,9 @@ def walk(L, seed, walk_id=0, steps=1000, table_log2=16, restart_period=0, target
     i32p = ctypes.POINTER(ctypes.c_int32)
     trp = tr.ctypes.data_as(i32p) if tr is not None else None
     scp = sc.ctypes.data_as(i32p) if sc is not None else None
-    if pq_capacity > 0:
+    if fi_perturb > 0:
+        rc = lib().ref_fi_walk(ctypes.byref(cfg), fi_perturb, ctypes.byref(res), trp, scp)
+    elif pq_capacity > 0:
         rc = lib().ref_pq_walk(ctypes.byref(cfg), pq_capacity, nbr_table_log2, ctypes.byref(res), trp, scp)
     else:
         rc = lib().ref_walk(ctypes.byref(cfg), ctypes.byref(res), trp, scp)
@@ -282,6 +290,14 @@ def walk(L, seed, walk_id=0, steps=1000, table_log2=16, restart_period=0, target
     if sc is not None:
         out["scores"] = sc[: res.steps_done]
     return out
+
+
+def perturb_indices(n: int, seed: int, walk_id: int, k: int, P: int):
+    """The free symbols that perturbation k of a first-improvement walk flips (in draw order)."""
+    out = np.zeros(P, dtype=np.int32)
+    got = lib().ref_perturb_indices(n, seed & 0xFFFFFFFFFFFFFFFF, walk_id, k, P,
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return [int(v) for v in out[:got]]
 
 
 def enum_skew(L: int):

@@ -118,6 +118,8 @@ def _python_best_first(L, seed, walk_id, steps, Q, nbr, nbr_log2=None):
             isl = _isl_np(L, x)
             HT, N2, queue = {x}, new_n2(), []
             trace.append((-1, isl))
+            if isl < best:  # a restart state counts like the initial state
+                best, best_step, best_x = isl, t + 1, x
             continue
         x, isl = f[3], f[0]
         HT.add(x)

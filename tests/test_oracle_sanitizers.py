@@ -1,7 +1,8 @@
 """The oracle under AddressSanitizer and UndefinedBehaviorSanitizer (host code, gcc): a small C
 driver includes the oracle source and runs every entry point the tests use on small inputs (the
 definitions, the one-flip scores, the walk with its bounded table, exact set, brute-force scoring
-and general sequences, the best-first search with and without the second table, the enumerations);
+and general sequences, the best-first search with and without the second table, the
+first-improvement search with its perturbation draw, the enumerations);
 any out-of-bounds access, leak or undefined operation fails the run."""
 import os
 import shutil
@@ -70,6 +71,12 @@ int main(void)
     c.watch_isl = -1;
     bad += check(ref_pq_walk(&c, 16, 0, &r, trace, stra) == 0, "best-first search");
     bad += check(ref_pq_walk(&c, 16, 5, &r, trace, stra) == 0, "best-first search, second table");
+    c.restart_period = 70;
+    bad += check(ref_fi_walk(&c, 3, &r, trace, stra) == 0 && r.traps > 0, "first-improvement search");
+    c.flags = ORACLE_BRUTE;
+    bad += check(ref_fi_walk(&c, 31, &r, trace, stra) == 0, "first-improvement search, all symbols");
+    int32_t picks[32];
+    ref_perturb_indices(191, 5, 9, 123, 32, picks);
 
     static int64_t all[1 << 8];
     bad += check(ref_enum_skew(15, all) == 0, "skew enumeration");

@@ -117,3 +117,55 @@ def test_trapped_walk_restarts():
     r = o.walk(5, SEED, 0, steps=40, trace=True, table_log2=8)
     assert r["traps"] >= 1 and r["restarts"] == r["traps"]
     assert -1 in r["trace"][:, 0]
+
+
+def _restart_every_step_statement(L, walk_id, steps):
+    """The walk with a restart after every step and an exact table, stated independently from the
+    start draws and the plain flip definition: from each start state x_r (occupied at step r) the
+    one move goes to its best flip (lowest index on ties; nothing but x_r is visited yet), occupied
+    at step r + 1, and the next start state follows at that same step."""
+    occupied = []
+    for r in range(steps):
+        x = o.start_bits(L, SEED, walk_id, r)
+        occupied.append((x, r))
+        j = int(np.argmin(o.flip_scores(L, x, brute=True)))
+        occupied.append((x ^ (1 << j), r + 1))
+    return occupied, [o.isl(o.skew_expand(L, x)) for x, _ in occupied]
+
+
+def test_restart_states_count_like_the_start_state():
+    # Every occupied state counts for best, hit and watch: the start state (step 0), each
+    # committed state, and each restart state (at the step after which it is occupied).  Found
+    # among 300 walks: some whose best is a restart state, and levels first met by a restart state.
+    L, S = 21, 40
+    n = (L + 1) // 2
+    best_from_restart = level_from_restart = 0
+    for w in range(300):
+        occ, isls = _restart_every_step_statement(L, w, S)
+        r = o.walk(L, SEED, w, steps=S, restart_period=1, table_log2=n + 1)
+        i = int(np.argmin(isls))  # first strict minimum
+        assert (r["best_isl"], r["best_step"], r["best_bits"]) == (isls[i], occ[i][1], occ[i][0]), w
+        assert r["restarts"] == S - 1 and r["steps_done"] == S
+        best_from_restart += i % 2 == 0 and i > 0
+        # a level met first by a restart state r >= 1: watch records its step, a target stops there
+        for k in range(2, len(occ), 2):
+            if min(isls[:k]) > isls[k]:
+                level = isls[k]
+                wr = o.walk(L, SEED, w, steps=S, restart_period=1, table_log2=n + 1, watch_isl=level)
+                assert wr["watch_step"] == occ[k][1] and wr["steps_done"] == S
+                tr = o.walk(L, SEED, w, steps=S, restart_period=1, table_log2=n + 1, target_isl=level)
+                assert tr["hit_step"] == occ[k][1] and tr["steps_done"] == occ[k][1]
+                assert tr["final_bits"] == occ[k][0] and tr["restarts"] == occ[k][1]
+                level_from_restart += 1
+                break
+    assert best_from_restart > 0 and level_from_restart > 0
+
+
+def test_trap_restart_state_counts():
+    # L = 5 (8 skew states) with an exact table traps every few steps; each trap's restart state
+    # is occupied at the trap step and counts for the best like any other state
+    r = o.walk(5, SEED, 0, steps=40, trace=True, table_log2=8)
+    start_isl = o.isl(o.skew_expand(5, o.start_bits(5, SEED, 0, 0)))
+    isl = np.concatenate([[start_isl], r["trace"][:, 1]])
+    assert r["traps"] >= 1
+    assert r["best_isl"] == isl.min() and r["best_step"] == int(np.argmin(isl))
