@@ -9,10 +9,11 @@ every walk to its start state and runs the job to completion on the GPU.
 Printed: one JSON line with the throughput in flip evaluations per second (the paper's speed
 unit, Section 3: one evaluated flip = one function evaluation), the roofline of the walk kernel,
 the oracle timed on the host cores on a bounded sample of the same workload, the plain
-one-walk-per-launch form on a sample, and time-to-F >= 8 statistics; then (unless --no-extras)
-an uneven batch of all 52 lengths, the serving workload, the exhaustive skew minimum at L = 61
-and 69, the best-first search with a bounded queue (with and without the second table), and
-the walk over general sequences at L = 192.
+one-walk-per-launch form on a sample, and time-to-target statistics (F >= 8, and the lower,
+labelled F >= 5 that most walks reach within the budget); then (unless --no-extras) the L = 101
+batch at low occupancy, an uneven batch of all 52 lengths, the serving workload, the exhaustive
+skew minimum at L = 61 and 69, the best-first search with a bounded queue (with and without the
+second table), and the walk over general sequences at L = 192.
 """
 import argparse
 import hashlib
@@ -33,13 +34,19 @@ STEPS = FLIP_BUDGET // (WALKS * N)  # 4768 steps per walk
 SEED = 2011000068
 TABLE_LOG2 = 16
 RESTART = 1 << 20
-TARGET_ISL = (L * L * 2) // (2 * 17)  # F >= 8.5  <=>  ISL <= floor(L^2 / 17) = 3825
-WATCH_ISL = (L * L * 1) // (2 * 8)  # F >= 8    <=>  ISL <= floor(L^2 / 16) = 4064
+# stop at F >= 8.5; record the first step at F >= 5 (the lower, labelled target most walks reach
+# within the budget).  Their integer ISL bounds (Eq. (3)) come from labs_isl_threshold in main().
+TARGET_F = (17, 2)
+WATCH_F = (5, 1)
+TARGET_ISL = WATCH_ISL = None
+F8_ISL = None  # F >= 8: reached by a walk exactly when its best ISL is at most this bound
 # algorithmic int32 operations per flip evaluation: for each of the (L-1)/2 even shifts,
 # u = s_{j+k} + s_{j-k}, t = C_k + sigma_j u, acc += t^2  (one add, two multiply-adds)
 ALG_OPS_PER_FLIP = 3 * (L - 1) // 2
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz int32 VALU lane-operations per second
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# MI355X published dense int8 matrix-core peak (no sparsity), operations per second
+INT8_MFMA_PEAK_TOPS = 5000.0
 KERNEL_SOURCES = ["paper_2011_00068_amd/csrc/walk_impl.hpp", "paper_2011_00068_amd/csrc/device_common.hpp",
                   "paper_2011_00068_amd/csrc/mfma_walker.hpp", "paper_2011_00068_amd/csrc/walk_inst_mfma.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_L255_16384_traffic.json")
@@ -53,21 +60,32 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
+def set_thresholds(labs):
+    """The integer ISL bounds of the stop, watch and F >= 8 levels (labs_isl_threshold, Eq. (3))."""
+    global TARGET_ISL, WATCH_ISL, F8_ISL
+    TARGET_ISL = labs.isl_threshold(L, *TARGET_F)  # 3825
+    WATCH_ISL = labs.isl_threshold(L, *WATCH_F)  # 6502
+    F8_ISL = labs.isl_threshold(L, 8, 1)  # 4064
+
+
 def cfgs(labs, walks, steps):
+    if TARGET_ISL is None:
+        set_thresholds(labs)
     return [labs.make_cfg(L, SEED, w, steps=steps, table_log2=TABLE_LOG2, restart_period=RESTART,
                           target_isl=TARGET_ISL, watch_isl=WATCH_ISL) for w in range(walks)]
 
 
-def time_to_f8(results, ms_per_job, steps):
-    """Time to the first F >= 8 state per walk: its step times the job's time per step (all walks
-    advance together).  Censored walks (no hit within the budget) count as never."""
+def time_to_target(results, ms_per_job, steps):
+    """Time to the first state at the watched F >= 5 per walk: its step times the job's time per
+    step (all walks advance together).  Censored walks (no hit within the budget) count as never,
+    so a percentile is reported only when at least that share of the walks hit."""
     import numpy as np
 
     hit = np.array([r["watch_step"] for r in results], dtype=np.int64)
     ok = hit >= 0
     frac = float(ok.mean())
     per_step_ms = ms_per_job / steps
-    out = {"threshold_F": 8.0, "isl_threshold": WATCH_ISL, "hit_fraction": frac,
+    out = {"threshold_F": WATCH_F[0] / WATCH_F[1], "isl_threshold": WATCH_ISL, "hit_fraction": frac,
            "censored": frac < 0.5, "p50_s": None, "p99_s": None}
     if ok.any():
         times = np.sort(np.where(ok, hit * per_step_ms / 1000.0, np.inf))
@@ -75,10 +93,19 @@ def time_to_f8(results, ms_per_job, steps):
         p99 = times[int(0.99 * (len(times) - 1))]
         out["p50_s"] = None if not np.isfinite(p50) else float(p50)
         out["p99_s"] = None if not np.isfinite(p99) else float(p99)
-    best = min(r["best_isl"] for r in results)
-    out["best_isl"] = int(best)
-    out["best_F"] = L * L / (2.0 * best)
     return out
+
+
+def time_to_f8(results):
+    """F >= 8 (ISL <= floor(L^2 / 16) = 4064): a walk reached it exactly when its best ISL is at
+    most that bound, so the hit fraction is exact without a watch level; its time is not recorded
+    (the watch level is F >= 5), so the percentiles are reported only as censored."""
+    import numpy as np
+
+    best = np.array([r["best_isl"] for r in results], dtype=np.int64)
+    frac = float((best <= F8_ISL).mean())
+    return {"threshold_F": 8.0, "isl_threshold": F8_ISL, "hit_fraction": frac, "censored": True,
+            "p50_s": None, "p99_s": None, "best_isl": int(best.min()), "best_F": L * L / (2.0 * best.min())}
 
 
 def cpu_baseline(budget_s=10.0):
@@ -126,7 +153,7 @@ def plain_form(labs, walks=32):
     per_walk_ms = dt * 1000.0 / walks
     return {"value": flips / dt, "unit": "flip-evals/s", "walks": walks,
             "ms_per_walk": per_walk_ms,
-            "time_to_F8": time_to_f8(res, per_walk_ms, STEPS)}, res
+            "time_to_F5": time_to_target(res, per_walk_ms, STEPS), "time_to_F8": time_to_f8(res)}, res
 
 
 def serving(labs, rate=20.0, n_requests=100, seed=SEED):
@@ -174,6 +201,7 @@ def uneven_batch(labs):
     cfg = [labs.make_cfg(L, SEED, w, steps=10 ** 6, table_log2=TABLE_LOG2) for L in range(201, 304, 2)
            for w in range(64)]
     plan = labs.WalkPlan(cfg, use_graph=True)
+    variant = plan.opts()["variant"]
     plan.run()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -183,10 +211,49 @@ def uneven_batch(labs):
     res = plan.results()
     plan.close()
     flips = sum(r["flip_evals"] for r in res)
+    alg = sum(r["flip_evals"] * 3 * (c.L - 1) // 2 for r, c in zip(res, cfg)) / (ms / 1000.0) / 1e12
     return {"walks": len(cfg), "steps_per_walk": 10 ** 6, "launches": launches, "hipgraph": True, "kernel_ms": ms,
             "flip_evals_per_s": flips / wall,
-            "alg_ops_frac_of_valu_peak": sum(r["flip_evals"] * 3 * (c.L - 1) // 2 for r, c in zip(res, cfg))
-            / (ms / 1000.0) / (VALU_PEAK_TOPS * 1e12)}
+            # the launch lasts as long as its slowest walk's 10^6 dependent steps
+            "us_per_step": ms * 1000.0 / 10 ** 6,
+            "roofline": matrix_or_alu_roofline(variant, alg)}
+
+
+def matrix_or_alu_roofline(variant, alg_tops):
+    """The walk kernel's roofline for alg_tops algorithmic TOP/s: the dense int8 matrix-core peak
+    when the flip scoring runs on the matrix cores (variant 3), else the int32 VALU peak."""
+    if variant == 3:
+        return {"bound": "mfma", "achieved": alg_tops, "peak": INT8_MFMA_PEAK_TOPS, "unit": "TOP/s",
+                "frac": alg_tops / INT8_MFMA_PEAK_TOPS}
+    return {"bound": "alu", "achieved": alg_tops, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+            "frac": alg_tops / VALU_PEAK_TOPS}
+
+
+def low_occupancy(labs, Lx=101, walks=1024, steps=10 ** 5):
+    """The L = 101 batch: 1,024 walks (one wavefront per SIMD) x 10^5 steps, visited tables of
+    2^16 words, one launch; throughput at low occupancy, where a step's dependent latency and not
+    the issue rate bounds the kernel."""
+    import torch
+
+    cfg = [labs.make_cfg(Lx, SEED, w, steps=steps, table_log2=TABLE_LOG2) for w in range(walks)]
+    plan = labs.WalkPlan(cfg)
+    opts = plan.opts()
+    plan.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.run()
+    ms, launches = plan.last_timing()
+    wall = time.perf_counter() - t0
+    res = plan.results()
+    plan.close()
+    flips = sum(r["flip_evals"] for r in res)
+    alg = flips * 3 * (Lx - 1) // 2 / (ms / 1000.0) / 1e12
+    best = min(r["best_isl"] for r in res)
+    return {"L": Lx, "walks": walks, "steps_per_walk": steps, "launches": launches, "kernel_ms": ms,
+            "flip_evals": flips, "flip_evals_per_s": flips / wall, "us_per_step": ms * 1000.0 / steps,
+            "kernel": "k_walk_mfma" if opts["variant"] == 3 else "k_walk", "plan_opts": opts,
+            "roofline": dict(matrix_or_alu_roofline(opts["variant"], alg), alg_ops_per_flip=3 * (Lx - 1) // 2),
+            "best_isl": best, "best_F": Lx * Lx / (2.0 * best)}
 
 
 def best_first(labs, walks=WALKS, steps=1000):
@@ -212,8 +279,9 @@ def best_first(labs, walks=WALKS, steps=1000):
 
 def general_walk(labs, Lg=192, walks=WALKS, steps=2000):
     """The walk over general sequences (all L symbols free, every shift counts) at the longest
-    supported length: flip evaluations per second and the ALU roofline with 3 (L-1) operations
-    per evaluation (one add and two multiply-adds per shift)."""
+    supported length: flip evaluations per second and the roofline with 3 (L-1) algorithmic
+    operations per evaluation (one add and two multiply-adds per shift) against the int8
+    matrix-core peak (its correlation sums run as int8 tiles)."""
     cfg = [labs.make_cfg(Lg, SEED, w, steps=steps, table_log2=TABLE_LOG2) for w in range(walks)]
     labs.general_walk_batch(cfg[:256])  # warm the launch path
     res, ms = labs.general_walk_batch(cfg)
@@ -222,8 +290,7 @@ def general_walk(labs, Lg=192, walks=WALKS, steps=2000):
     best = min(r["best_isl"] for r in res)
     return {"L": Lg, "walks": walks, "steps_per_walk": steps, "kernel_ms": ms, "flip_evals": evals,
             "flip_evals_per_s": evals / (ms / 1000.0),
-            "roofline": {"bound": "alu", "achieved": alg, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                         "frac": alg / VALU_PEAK_TOPS, "alg_ops_per_flip": 3 * (Lg - 1)},
+            "roofline": dict(matrix_or_alu_roofline(3, alg), alg_ops_per_flip=3 * (Lg - 1)),
             "best_isl": best, "best_F": Lg * Lg / (2.0 * best)}
 
 
@@ -236,7 +303,9 @@ def enum_alg_ops_per_group(Lx):
 
 def enumeration(labs, lengths=(61, 69)):
     """The whole skew space of each length, minimum ISL by exhaustive search on the GPU (one
-    sequence scored per symmetry group of four)."""
+    sequence scored per symmetry group of four).  The roofline counts the word operations of the
+    (sequence, lag) pairs the branch and bound actually evaluated (the kernel reports them); the
+    exhaustive count is given beside it."""
     out = []
     for Lx in lengths:
         labs.enum_skew_min(Lx, 0, 1 << 12)  # warm the launch path
@@ -244,13 +313,16 @@ def enumeration(labs, lengths=(61, 69)):
         r = labs.enum_skew_min(Lx)
         wall = time.perf_counter() - t0
         groups = r["states"] // 4
-        alg = groups * enum_alg_ops_per_group(Lx) / (r["kernel_ms"] / 1000.0) / 1e12
+        alg = r["word_ops"] / (r["kernel_ms"] / 1000.0) / 1e12
+        exhaustive = groups * enum_alg_ops_per_group(Lx)
         out.append({"L": Lx, "sequences": r["states"], "min_isl": r["min_isl"],
                     "F": Lx * Lx / (2.0 * r["min_isl"]), "optimal_sequences": r["count"],
                     "first_x": hex(r["first_x"]), "kernel_ms": r["kernel_ms"], "wall_s": wall,
                     "sequences_per_s": r["states"] / wall,
                     "roofline": {"bound": "alu", "achieved": alg, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                                 "frac": alg / VALU_PEAK_TOPS,
+                                 "frac": alg / VALU_PEAK_TOPS, "word_ops_evaluated": r["word_ops"],
+                                 "word_ops_exhaustive": exhaustive,
+                                 "evaluated_share": r["word_ops"] / exhaustive,
                                  "alg_ops_per_group": enum_alg_ops_per_group(Lx)}})
     return out
 
@@ -303,6 +375,9 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--only", choices=["low_occupancy", "uneven_batch", "serving", "enumeration", "best_first",
+                                       "general_walk"],
+                    help="run only this measurement and print its JSON (for profiling)")
     ap.add_argument("--probe-lds", action="store_true",
                     help="only measure the LDS read bandwidth (4-, 8- and 16-byte reads per lane) and exit")
     args = ap.parse_args()
@@ -335,6 +410,12 @@ def main():
     import paper_2011_00068_amd as labs
 
     torch.cuda.set_device(0)
+    set_thresholds(labs)
+    if args.only:
+        legs = {"low_occupancy": low_occupancy, "uneven_batch": uneven_batch, "serving": serving,
+                "enumeration": enumeration, "best_first": best_first, "general_walk": general_walk}
+        print(json.dumps({args.only: legs[args.only](labs)}), flush=True)
+        return
     plan = labs.WalkPlan(cfgs(labs, WALKS, STEPS), variant=args.variant)
     opts = plan.opts()
     for _ in range(args.warmup):
@@ -361,19 +442,29 @@ def main():
     alg_ops_per_launch = flips_per_job * ALG_OPS_PER_FLIP / max(1, launches)
     achieved = alg_ops_per_launch / (per_launch_ms / 1000.0) / 1e12
     cnt = counter_summary()
-    roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / VALU_PEAK_TOPS,
-                "traffic": cnt["hbm_bytes_per_launch"] if cnt else None,
-                "kernel": "k_walk_mfma" if opts["variant"] == 3 else "k_walk",
-                "kernel_ms_per_launch": per_launch_ms,
-                "alg_ops_per_flip": ALG_OPS_PER_FLIP,
-                # rocprofv3 counters of the same launch: share of VALU issue cycles in use, and
-                # VALU instructions per walk step (128 flip evaluations)
-                "counter_valu_issue_frac": cnt["valu_issue_busy_frac"] if cnt else None,
-                "counter_valu_insts_per_step": cnt["valu_insts_per_step"] if cnt else None,
-                "counter_salu_issue_frac": cnt.get("salu_issue_busy_frac") if cnt else None,
-                "counter_mfma_insts_per_step": cnt.get("mfma_insts_per_step") if cnt else None,
-                "lds": lds_summary(labs, cnt)}
+    # The flip scoring's correlation sums run as int8 x int8 -> int32 matrix-core tiles, so the
+    # roof of the algorithmic operations (381 per evaluation) is the dense int8 peak.  The kernel
+    # is far below it: each walk's product is three small tiles on a serial chain, and the roof
+    # that binds is instruction issue (the VALU, SALU and LDS-pipe shares from the counters).
+    roofline = dict(matrix_or_alu_roofline(opts["variant"], achieved),
+                    traffic=cnt["hbm_bytes_per_launch"] if cnt else None,
+                    kernel="k_walk_mfma" if opts["variant"] == 3 else "k_walk",
+                    kernel_ms_per_launch=per_launch_ms,
+                    alg_ops_per_flip=ALG_OPS_PER_FLIP,
+                    binding={"roof": "VALU issue",
+                             # rocprofv3 counters of the same launch: share of the SIMDs' VALU
+                             # issue cycles in use (VALU instructions x 4 cycles per wave64
+                             # instruction / SIMD cycles), and the same for SALU and the LDS pipe
+                             "valu_issue_frac": cnt["valu_issue_busy_frac"] if cnt else None,
+                             "salu_issue_frac": cnt.get("salu_issue_busy_frac") if cnt else None,
+                             "lds_pipe_frac": cnt.get("lds_active_frac") if cnt else None,
+                             "valu_insts_per_step": cnt["valu_insts_per_step"] if cnt else None,
+                             "mfma_insts_per_step": cnt.get("mfma_insts_per_step") if cnt else None},
+                    lds=lds_summary(labs, cnt))
+    if opts["variant"] != 3:
+        # the bit-sliced and direct layouts execute another number of operations per evaluation
+        # than the algorithmic count, so no fraction of a peak is claimed for them
+        roofline["frac"] = None
 
     line = {
         "metric": "flip-evals/s at L=255 (batched walks, % INT32 VALU peak); p50 time-to-F>=8",
@@ -386,17 +477,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32",
+        "dtype": "int8xint8->int32 MFMA + int32 VALU",
         "data": "synthetic",
         "config": {"workload": "L255_16384walks_1e10flips", "L": L, "walks": WALKS,
                    "steps_per_walk": STEPS, "table_log2": TABLE_LOG2, "restart_period": RESTART,
-                   "target_F": 8.5, "parallelism": "none (1 GPU)", "plan_opts": opts},
+                   "target_F": 8.5, "watch_F": WATCH_F[0] / WATCH_F[1], "parallelism": "none (1 GPU)",
+                   # persistent = 1: one wave per walk, hardware-dispatched (not the pulling grid)
+                   "plan_opts": opts},
         "roofline": roofline,
-        "time_to_F8": time_to_f8(res, ms_per_step, STEPS),
+        "time_to_F5": time_to_target(res, ms_per_step, STEPS),
+        "time_to_F8": time_to_f8(res),
     }
     if not args.no_plain:
         line["plain_form"], _ = plain_form(labs)
     if not args.no_extras:
+        line["low_occupancy"] = low_occupancy(labs)
         line["uneven_batch"] = uneven_batch(labs)
         line["serving"] = serving(labs)
         line["enumeration"] = enumeration(labs)

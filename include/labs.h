@@ -25,8 +25,9 @@
  *   - stream: a hipStream_t passed as void*; NULL = the default (null) stream.  Entry points
  *     whose name ends in _dev are asynchronous on that stream unless stated otherwise; all
  *     others are synchronous.
- *   - Every computation runs in the library's gfx950 kernels; there is no CPU fallback.  A
- *     missing or unusable GPU returns LABS_EDEVICE.
+ *   - Every computation of the search runs in the library's gfx950 kernels; there is no CPU
+ *     fallback.  A missing or unusable GPU returns LABS_EDEVICE.  (labs_isl_threshold, which only
+ *     converts a stop parameter, is host integer arithmetic.)
  */
 #ifndef LABS_H
 #define LABS_H
@@ -78,6 +79,13 @@ int labs_isl(int32_t L, const int8_t *s, int64_t *isl_out);
 /* Merit factor of one sequence (Eq. (3)).  As labs_isl; L == 1 (ISL = 0) gives LABS_EDOM. */
 int labs_merit(int32_t L, const int8_t *s, double *F_out);
 
+/* Integer form of a merit-factor threshold (Eq. (3)): F >= num/den holds at length L exactly when
+ * ISL <= floor(L^2 * den / (2 * num)), since F = L^2 / (2 ISL) with ISL > 0.  Walks, searches and
+ * the server compare integer ISL with this bound, never a rounded F.  Host integer arithmetic only
+ * (a conversion of a stop parameter; no device work).  1 <= L <= 65535, num > 0, den > 0, else
+ * LABS_EINVAL; a bound above INT64_MAX is clamped to it.  isl_out: host. */
+int labs_isl_threshold(int32_t L, int64_t num, int64_t den, int64_t *isl_out);
+
 /* Batched Eq. (1)-(3) and the PSL of Section 1 (max_{k>=1} |C_k|) for `count` sequences of
  * length L stored back to back (row r at s_dev + r*L).  Device buffers: s_dev (count*L int8),
  * isl_dev (count int64), F_dev (count double, -1.0 where ISL = 0; may be NULL), psl_dev (count
@@ -99,12 +107,17 @@ int labs_enum_skew_dev(int32_t L, int32_t *isl_dev, void *stream);
  * {x, x^A, x^O, x^A^O} with x = r << 2, and the groups partition the 2^n sequences.  The call
  * covers groups r_begin .. r_end - 1 (r_begin = 0, r_end = 2^(n-2): the whole space) and reports
  * the lowest ISL, how many covered sequences reach it (always a multiple of 4), the lowest such
- * free-bit vector x (bit j = 1 <=> s_j = -1), the sequences covered, and the device time of the
- * enumeration kernels.  Odd 3 <= L <= 125 (n <= 63).  An empty block (r_begin == r_end) gives
- * min_isl = -1, count = first_x = states = 0.  Blocking: the work runs on `stream` (NULL = the
- * default stream) and the call returns when it is done; it allocates and frees a small device
- * buffer (32 bytes per resident block).  LABS_EINVAL for a bad L, r_begin > r_end or r_end >
- * 2^(n-2). */
+ * free-bit vector x (bit j = 1 <=> s_j = -1), the sequences covered, the device time of the
+ * enumeration kernels, and the work they did: word_ops sums 3 ceil((L-k)/32) + 2 word operations
+ * (funnel shift, masked xor and popcount per 32-bit word of the L-k overlapping positions, then
+ * C_k^2) over the (sequence, even lag k) pairs evaluated.  The search is branch and bound: once
+ * the partial ISL of every sequence of a pass exceeds the lowest ISL found, the pass's remaining
+ * lags are skipped (they cannot change the minimum, its multiplicity or its lowest argument), so
+ * word_ops is below the exhaustive count.  Odd 3 <= L <= 125 (n <= 63).  An empty block (r_begin
+ * == r_end) gives min_isl = -1, count = first_x = states = word_ops = 0.  Blocking: the work runs
+ * on `stream` (NULL = the default stream) and the call returns when it is done; it allocates and
+ * frees a small device buffer (32 bytes per resident block).  LABS_EINVAL for a bad L, r_begin >
+ * r_end or r_end > 2^(n-2). */
 typedef struct labs_enum_min_result {
     int32_t min_isl;
     int32_t reserved;
@@ -112,6 +125,7 @@ typedef struct labs_enum_min_result {
     uint64_t first_x;
     uint64_t states;
     double kernel_ms;
+    uint64_t word_ops;
 } labs_enum_min_result;
 
 int labs_enum_skew_min(int32_t L, uint64_t r_begin, uint64_t r_end, labs_enum_min_result *out,
@@ -146,11 +160,15 @@ int labs_flip_scores_dev(int32_t L, int32_t count, const uint32_t *x_dev, int32_
  *     the hash; an insert overwrites.  The start state is inserted; so is every committed state.
  *   - every step scores n flips (n flip evaluations, the paper's speed unit of Section 3); if
  *     every flip leads to a visited state the walk restarts (a trap; the step still counts).
- *   - best: strict improvement only (the first best is kept); restart states do not update it.
+ *   - best: strict improvement only (the first best is kept).  Every occupied state counts for
+ *     best, target and watch: the initial state (step 0), each committed state, and each restart
+ *     state (a restart repeats the initialisation), occupied at the step after which the restart
+ *     happens (the trap step, or the step completing the period).
  *   - after a committed step t: if ISL <= target_isl the walk records hit_step = t and stops;
  *     if ISL <= watch_isl it records watch_step = t (first time) and goes on; if the budget
  *     `steps` is reached it stops; otherwise if restart_period > 0 and t % restart_period == 0
- *     it restarts.  A start state (t = 0) that already meets target / watch records step 0.
+ *     it restarts, and the restart state is checked the same way at step t.  A start state
+ *     (t = 0) that already meets target / watch records step 0.
  * ------------------------------------------------------------------------------------------- */
 
 typedef struct labs_walk_cfg {
@@ -247,6 +265,35 @@ int labs_pq_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, const labs_pq_
                        void *stream);
 
 /* ---------------------------------------------------------------------------------------------
+ * First-improvement search with perturbations: the method of Dimitrov et al. as Section 2
+ * describes it.  From the current skew-symmetric state the search moves at once to the first flip
+ * j = 0, 1, ..., c (index order) whose ISL is strictly lower than the current ISL, and scans again
+ * from the new state; when no flip improves (a local minimum of the one-flip neighbourhood) it
+ * flips perturb_bits distinct free symbols drawn at random and goes on from the perturbed state,
+ * whatever its ISL.  Perturbation k of a walk (k = 0, 1, ... over the whole walk) draws 64-bit
+ * words sm(sm(sm(seed, walk_id), 2^32 + k), i), i = 0, 1, ... (sm as for the start states) and
+ * flips j = floor((word >> 32) * n / 2^32) for each word whose j was not drawn before, until
+ * perturb_bits symbols are flipped (or 65536 words are used).  There is no visited table
+ * (table_log2 is checked but unused).  One step = one scan; flip_evals counts j + 1 for a move at
+ * flip j and n + perturb_bits for a perturbation (the flips the sequential method evaluates);
+ * traps counts the perturbations; trace records (j of the move, or -1 for a perturbation; ISL
+ * after the step); scores (LABS_TRACE_SCORES) the ISL of every flip of the state each step starts
+ * from.  Start states, restarts, target, watch and best follow the walk above.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct labs_fi_opts {
+    int32_t perturb_bits; /* symbols flipped by a perturbation: 1 <= perturb_bits <= min(n, 32) */
+    int32_t reserved;
+} labs_fi_opts;
+
+/* Runs n_walks first-improvement searches to completion (one launch per kernel shape; steps <
+ * 2^31 per walk) and copies the results to out (host).  trace / scores as for labs_walk_batch.
+ * kernel_ms (may be NULL): device time of the search launches.  Synchronous on stream.  Allocates
+ * and frees its device state.  LABS_EINVAL for a bad walk configuration or perturb_bits. */
+int labs_fi_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, const labs_fi_opts *opts,
+                       labs_walk_result *out, int32_t *trace, int32_t *scores, double *kernel_ms,
+                       void *stream);
+
+/* ---------------------------------------------------------------------------------------------
  * The walk over general (not skew-symmetric) sequences: the unrestricted problem that the
  * skew-symmetric restriction of Section 1 reduces.  Exactly the walk of labs_walk_batch with
  * n = L free symbols (bit j of x = b_j, drawn as the skew start's words over L bits), a flip
@@ -294,11 +341,20 @@ int labs_walk_plan_get_opts(const labs_walk_plan *plan, labs_plan_opts *opts);
 int labs_walk_plan_last_timing(const labs_walk_plan *plan, double *ms, int32_t *launches);
 void labs_walk_plan_destroy(labs_walk_plan *plan);
 
-/* Times the kernel variants / launch shapes on a short synthetic walk batch at length L and
- * stores the fastest in the autotune cache (file named by $LABS_AUTOTUNE_CACHE, default
- * ~/.cache/liblabs_autotune.txt; entries keyed by device arch and L).  Tuning never changes
- * results.  best (host, may be NULL) receives the winner. */
+/* Times the kernel variants / launch shapes (variant, waves_per_block, probe_width, persistent)
+ * on a short synthetic walk batch of n_walks walks at length L and stores the fastest in the
+ * autotune cache (file named by $LABS_AUTOTUNE_CACHE, default ~/.cache/liblabs_autotune.txt;
+ * entries keyed by device arch and L).  Plans created afterwards with automatic options take the
+ * cached entry of their own L, else of the nearest L tuned for the same kernel shape (walks of
+ * one length), or the entry of their own key (mixed lengths, see labs_autotune_batch).  Tuning
+ * never changes results.  best (host, may be NULL) receives the winner. */
 int labs_autotune(int32_t L, int32_t n_walks, labs_plan_opts *best);
+
+/* As labs_autotune, timed on the caller's batch (cfg: host array, as for labs_walk_plan_create)
+ * with every walk cut to at most 512 steps, without traces, target or watch.  A batch of mixed
+ * lengths is keyed by its shortest and longest length and only plans of that same range take
+ * its entry.  LABS_EINVAL for n_walks < 1, a NULL cfg or a bad walk configuration. */
+int labs_autotune_batch(int32_t n_walks, const labs_walk_cfg *cfg, labs_plan_opts *best);
 
 /* ---------------------------------------------------------------------------------------------
  * Serving: a request loop that admits search jobs by device memory for their walk state, keeps

@@ -42,11 +42,11 @@ JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_CANCELLED = 0, 1, 2, 3
 # Every symbol include/labs.h declares (checked by the tests).
 EXPORTS = [
     "labs_strerror", "labs_last_error", "labs_device_info", "labs_probe_lds_read",
-    "labs_isl", "labs_merit", "labs_isl_batch_dev", "labs_enum_skew_dev", "labs_enum_skew_min",
+    "labs_isl", "labs_merit", "labs_isl_threshold", "labs_isl_batch_dev", "labs_enum_skew_dev", "labs_enum_skew_min",
     "labs_flip_scores_dev",
     "labs_walk_batch", "labs_walk_plan_create", "labs_walk_plan_run", "labs_walk_plan_results",
     "labs_walk_plan_get_opts", "labs_walk_plan_last_timing", "labs_walk_plan_destroy",
-    "labs_autotune", "labs_pq_walk_batch", "labs_general_walk_batch", "labs_general_flip_scores_dev",
+    "labs_autotune", "labs_autotune_batch", "labs_pq_walk_batch", "labs_fi_walk_batch", "labs_general_walk_batch", "labs_general_flip_scores_dev",
     "labs_server_create", "labs_search_submit", "labs_search_poll", "labs_search_wait",
     "labs_search_cancel", "labs_server_stats", "labs_server_destroy",
 ]
@@ -114,11 +114,16 @@ class EnumMinResult(ctypes.Structure):
         ("first_x", ctypes.c_uint64),
         ("states", ctypes.c_uint64),
         ("kernel_ms", ctypes.c_double),
+        ("word_ops", ctypes.c_uint64),
     ]
 
 
 class PqOpts(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_int32), ("nbr_table_log2", ctypes.c_int32)]
+
+
+class FiOpts(ctypes.Structure):
+    _fields_ = [("perturb_bits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -185,6 +190,7 @@ def lib():
     L.labs_probe_lds_read.argtypes = [i32, P(ctypes.c_double), P(ctypes.c_double)]
     L.labs_isl.argtypes = [i32, vp, P(i64)]
     L.labs_merit.argtypes = [i32, vp, P(ctypes.c_double)]
+    L.labs_isl_threshold.argtypes = [i32, i64, i64, P(i64)]
     L.labs_isl_batch_dev.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp]
     L.labs_enum_skew_dev.argtypes = [i32, vp, vp]
     L.labs_enum_skew_min.argtypes = [i32, u64, u64, P(EnumMinResult), vp]
@@ -198,8 +204,10 @@ def lib():
     L.labs_walk_plan_destroy.argtypes = [vp]
     L.labs_walk_plan_destroy.restype = None
     L.labs_autotune.argtypes = [i32, i32, P(PlanOpts)]
+    L.labs_autotune_batch.argtypes = [i32, P(WalkCfg), P(PlanOpts)]
     L.labs_pq_walk_batch.argtypes = [i32, P(WalkCfg), P(PqOpts), P(WalkResult), vp, vp,
                                      P(ctypes.c_double), vp]
+    L.labs_fi_walk_batch.argtypes = [i32, P(WalkCfg), P(FiOpts), P(WalkResult), vp, vp, P(ctypes.c_double), vp]
     L.labs_general_walk_batch.argtypes = [i32, P(WalkCfg), P(WalkResult), vp, vp, P(ctypes.c_double), vp]
     L.labs_general_flip_scores_dev.argtypes = [i32, i32, vp, vp, vp]
     L.labs_server_create.argtypes = [P(ServerOpts), P(vp)]
@@ -292,14 +300,15 @@ def enum_skew(L, device="cuda"):
 
 def enum_skew_min(L, r_begin=0, r_end=None):
     """Lowest ISL over the symmetry groups r_begin .. r_end - 1 of the odd-length-L skew space
-    (the whole space by default): {"min_isl", "count", "first_x", "states", "kernel_ms"}."""
+    (the whole space by default): {"min_isl", "count", "first_x", "states", "kernel_ms",
+    "word_ops"}."""
     n = (L + 1) // 2
     if r_end is None:
         r_end = 1 << max(0, n - 2)
     res = EnumMinResult()
     _check(lib().labs_enum_skew_min(L, r_begin, r_end, ctypes.byref(res), _stream()), "labs_enum_skew_min")
     return {"min_isl": res.min_isl, "count": res.count, "first_x": res.first_x, "states": res.states,
-            "kernel_ms": res.kernel_ms}
+            "kernel_ms": res.kernel_ms, "word_ops": res.word_ops}
 
 
 def x_words(x: int):
@@ -480,6 +489,31 @@ def pq_walk_batch(cfgs, capacity, nbr_table_log2=0, stream=None):
     return out, ms.value
 
 
+def fi_walk_batch(cfgs, perturb_bits=3, stream=None):
+    """labs_fi_walk_batch: first-improvement searches with perturbations of perturb_bits symbols;
+    returns (result dicts with traces if asked, device milliseconds).  traps = perturbations."""
+    cfgs = list(cfgs)
+    arr = (WalkCfg * len(cfgs))(*cfgs)
+    res = (WalkResult * len(cfgs))()
+    tr = sum(c.steps for c in cfgs if c.flags & TRACE)
+    sc = sum(c.steps * ((c.L + 1) // 2) for c in cfgs if c.flags & TRACE_SCORES)
+    tbuf = ctypes.create_string_buffer(8 * tr) if tr else None
+    sbuf = ctypes.create_string_buffer(4 * sc) if sc else None
+    ms = ctypes.c_double()
+    s = _stream() if stream is None else ctypes.c_void_p(stream)
+    opts = FiOpts(perturb_bits, 0)
+    _check(lib().labs_fi_walk_batch(len(cfgs), arr, ctypes.byref(opts), res, tbuf, sbuf, ctypes.byref(ms), s),
+           "labs_fi_walk_batch")
+    out = [_result_dict(res[i], (cfgs[i].L + 1) // 2) for i in range(len(cfgs))]
+    traces, scores = _split_traces(cfgs, tbuf.raw if tbuf else b"", sbuf.raw if sbuf else b"")
+    for i in range(len(cfgs)):
+        if traces[i] is not None:
+            out[i]["trace"] = traces[i]
+        if scores[i] is not None:
+            out[i]["scores"] = scores[i]
+    return out, ms.value
+
+
 def general_walk_batch(cfgs, stream=None):
     """labs_general_walk_batch: walks over general (not skew-symmetric) sequences; returns
     (result dicts with traces if asked, device milliseconds).  Bits cover all L symbols."""
@@ -505,16 +539,28 @@ def general_walk_batch(cfgs, stream=None):
 
 
 def autotune(L, n_walks):
+    """labs_autotune: the fastest launch form for n_walks walks of length L (stored in the cache)."""
     o = PlanOpts()
     _check(lib().labs_autotune(L, n_walks, ctypes.byref(o)), "labs_autotune")
+    return {f: getattr(o, f) for f, _ in PlanOpts._fields_}
+
+
+def autotune_batch(cfgs):
+    """labs_autotune_batch: the fastest launch form for this batch of walk configurations."""
+    cfgs = list(cfgs)
+    arr = (WalkCfg * len(cfgs))(*cfgs)
+    o = PlanOpts()
+    _check(lib().labs_autotune_batch(len(cfgs), arr, ctypes.byref(o)), "labs_autotune_batch")
     return {f: getattr(o, f) for f, _ in PlanOpts._fields_}
 
 
 # --- serving -----------------------------------------------------------------------------------
 
 def isl_threshold(L, num, den):
-    """Integer form of F >= num/den at length L (Eq. (3)): ISL <= floor(L^2 den / (2 num))."""
-    return (L * L * den) // (2 * num)
+    """labs_isl_threshold: the integer form of F >= num/den at length L (Eq. (3))."""
+    out = ctypes.c_int64()
+    _check(lib().labs_isl_threshold(int(L), int(num), int(den), ctypes.byref(out)), "labs_isl_threshold")
+    return out.value
 
 
 class Server:

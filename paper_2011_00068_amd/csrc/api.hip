@@ -228,6 +228,19 @@ extern "C" int labs_merit(int32_t L, const int8_t *s, double *F_out)
     return isl_one(L, s, nullptr, F_out);
 }
 
+extern "C" int labs_isl_threshold(int32_t L, int64_t num, int64_t den, int64_t *isl_out)
+{
+    if (!isl_out)
+        return fail(LABS_EINVAL, "NULL isl_out");
+    if (L < 1 || L > 65535 || num <= 0 || den <= 0)
+        return fail(LABS_EINVAL, "labs_isl_threshold: L = %d, num = %lld, den = %lld (need 1 <= L <= 65535, "
+                    "num > 0, den > 0)", L, (long long)num, (long long)den);
+    // F >= num/den  <=>  L^2 / (2 ISL) >= num/den  <=>  ISL <= L^2 den / (2 num)   (Eq. (3))
+    const __int128 v = (__int128)L * L * den / ((__int128)2 * num);
+    *isl_out = (int64_t)std::min<__int128>(v, (__int128)INT64_MAX);
+    return LABS_OK;
+}
+
 extern "C" int labs_isl_batch_dev(int32_t L, int32_t count, const int8_t *s_dev, int64_t *isl_dev, double *F_dev,
                                   int32_t *psl_dev, int32_t *corr_dev, void *stream)
 {
@@ -307,6 +320,7 @@ extern "C" int labs_enum_skew_min(int32_t L, uint64_t r_begin, uint64_t r_end, l
     out->first_x = res.min_isl == 0xFFFFFFFFu ? 0 : res.first_x;
     out->states = 4 * (r_end - r_begin);
     out->kernel_ms = (double)ms;
+    out->word_ops = res.word_ops;
     return LABS_OK;
 }
 
@@ -662,9 +676,15 @@ namespace liblabs {
 
 // The synchronous one-launch-per-shape batches: the best-first search (nlog2, cap) and the
 // general walk (general = true).
-static int batch_sync(bool general, int32_t n_walks, const labs_walk_cfg *cfg, int cap, int nlog2,
+// The searches run to completion by one launch per kernel shape: the best-first search (cap,
+// nlog2), the general walk, the first-improvement search (cap = perturbation size, no tables).
+enum BatchKind { kBatchPq, kBatchGeneral, kBatchFi };
+
+static int batch_sync(BatchKind kind, int32_t n_walks, const labs_walk_cfg *cfg, int cap, int nlog2,
                       labs_walk_result *out, int32_t *trace, int32_t *scores, double *kernel_ms, void *stream)
 {
+    const bool general = kind == kBatchGeneral;
+    const char *what = general ? "labs_general_walk_batch" : (kind == kBatchFi ? "labs_fi_walk_batch" : "labs_pq_walk_batch");
     int rc = check_device();
     if (rc)
         return rc;
@@ -685,7 +705,8 @@ static int batch_sync(bool general, int32_t n_walks, const labs_walk_cfg *cfg, i
         w.target_isl = c.target_isl;
         w.watch_isl = c.watch_isl;
         w.table_offset = table_words;
-        table_words += (int64_t)1 << c.table_log2;
+        if (kind != kBatchFi)
+            table_words += (int64_t)1 << c.table_log2;
         w.trace_offset = (c.flags & LABS_TRACE) ? trace_records : -1;
         if (c.flags & LABS_TRACE)
             trace_records += c.steps;
@@ -721,7 +742,7 @@ static int batch_sync(bool general, int32_t n_walks, const labs_walk_cfg *cfg, i
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     float ms = 0.0f;
     hipError_t e = hipMalloc(&d_st, sizeof(WalkState) * (size_t)n_walks);
-    if (e == hipSuccess) e = hipMalloc(&d_tables, sizeof(uint64_t) * (size_t)table_words);
+    if (e == hipSuccess && table_words > 0) e = hipMalloc(&d_tables, sizeof(uint64_t) * (size_t)table_words);
     if (e == hipSuccess && nlog2 > 0) e = hipMalloc(&d_nbr, sizeof(uint64_t) * ((size_t)n_walks << nlog2));
     if (e == hipSuccess && trace_records > 0) e = hipMalloc(&d_trace, sizeof(int32_t) * 2 * (size_t)trace_records);
     if (e == hipSuccess && score_entries > 0) e = hipMalloc(&d_scores, sizeof(int32_t) * (size_t)score_entries);
@@ -739,6 +760,8 @@ static int batch_sync(bool general, int32_t n_walks, const labs_walk_cfg *cfg, i
             continue;
         if (general)
             e = launch_walk_general(sh, d_st, cnt, d_order + first[(size_t)sh], d_tables, d_trace, d_scores, s);
+        else if (kind == kBatchFi)
+            e = launch_fi_walk(sh, d_st, cnt, d_order + first[(size_t)sh], cap, d_trace, d_scores, s);
         else
             e = launch_pq_walk(sh, d_st, cnt, d_order + first[(size_t)sh], d_tables, d_nbr, nlog2, cap, d_trace,
                                d_scores, s);
@@ -760,7 +783,7 @@ static int batch_sync(bool general, int32_t n_walks, const labs_walk_cfg *cfg, i
     if (d_scores) (void)hipFree(d_scores);
     if (d_order) (void)hipFree(d_order);
     if (e != hipSuccess)
-        return hip_fail(e, general ? "labs_general_walk_batch" : "labs_pq_walk_batch");
+        return hip_fail(e, what);
     for (int32_t i = 0; i < n_walks; i++) {
         const WalkState &w = st[(size_t)i];
         labs_walk_result &r = out[i];
@@ -803,8 +826,28 @@ extern "C" int labs_pq_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, con
         if (cfg[i].steps >= ((int64_t)1 << 31))
             return fail(LABS_EINVAL, "labs_pq_walk_batch: walk %d: steps must be below 2^31", i);
     }
-    return batch_sync(false, n_walks, cfg, opts->capacity, opts->nbr_table_log2, out, trace, scores, kernel_ms,
+    return batch_sync(kBatchPq, n_walks, cfg, opts->capacity, opts->nbr_table_log2, out, trace, scores, kernel_ms,
                       stream);
+}
+
+extern "C" int labs_fi_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg, const labs_fi_opts *opts,
+                                  labs_walk_result *out, int32_t *trace, int32_t *scores, double *kernel_ms,
+                                  void *stream)
+{
+    if (n_walks < 1 || !cfg || !opts || !out)
+        return fail(LABS_EINVAL, "labs_fi_walk_batch: n_walks = %d with cfg, opts and out required", n_walks);
+    for (int32_t i = 0; i < n_walks; i++) {
+        int rc = walk_cfg_check(cfg[i], i);
+        if (rc)
+            return rc;
+        if (cfg[i].steps >= ((int64_t)1 << 31))
+            return fail(LABS_EINVAL, "labs_fi_walk_batch: walk %d: steps must be below 2^31", i);
+        const int n = (cfg[i].L + 1) / 2;
+        if (opts->perturb_bits < 1 || opts->perturb_bits > 32 || opts->perturb_bits > n)
+            return fail(LABS_EINVAL, "labs_fi_walk_batch: walk %d: perturb_bits = %d must be in [1, min(n, 32)] "
+                        "(n = %d)", i, opts->perturb_bits, n);
+    }
+    return batch_sync(kBatchFi, n_walks, cfg, opts->perturb_bits, 0, out, trace, scores, kernel_ms, stream);
 }
 
 extern "C" int labs_general_flip_scores_dev(int32_t L, int32_t count, const uint32_t *x_dev, int32_t *scores_dev,
@@ -837,7 +880,7 @@ extern "C" int labs_general_walk_batch(int32_t n_walks, const labs_walk_cfg *cfg
         if (c.steps > ((int64_t)1 << 30))
             return fail(LABS_EINVAL, "labs_general_walk_batch: walk %d: steps must be at most 2^30", i);
     }
-    return batch_sync(true, n_walks, cfg, 0, 0, out, trace, scores, kernel_ms, stream);
+    return batch_sync(kBatchGeneral, n_walks, cfg, 0, 0, out, trace, scores, kernel_ms, stream);
 }
 
 // =============================================================================================
@@ -856,28 +899,48 @@ static std::string cache_path()
     return std::string(home ? home : "/tmp") + "/.cache/liblabs_autotune.txt";
 }
 
-// cache lines: "<arch> <L> <variant> <waves_per_block> <probe_width> <persistent>".  Later entries
-// win; an entry for L itself wins over the nearest L tuned for the same kernel shape.
-static bool cache_lookup(int L, labs_plan_opts *o)
+// Cache key of a batch: "<L>" when every walk has length L, "M<minL>-<maxL>" for a batch of
+// mixed lengths (they run the dispatching kernel, so a single-length entry does not describe
+// them).
+static std::string batch_key(int minL, int maxL)
+{
+    return minL == maxL ? std::to_string(maxL) : "M" + std::to_string(minL) + "-" + std::to_string(maxL);
+}
+
+// cache lines: "<arch> <key> <variant> <waves_per_block> <probe_width> <persistent>".  Later
+// entries win.  A single-length batch takes the entry of its own L, else that of the nearest L
+// tuned for the same kernel shape; a mixed batch takes only an entry of its own key.
+static bool cache_lookup(int minL, int maxL, labs_plan_opts *o)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     std::ifstream f(cache_path());
     if (!f)
         return false;
     const std::string arch = device_arch();
-    const int shape = shape_for_length(L);
+    const bool mixed = minL != maxL;
+    const std::string want = batch_key(minL, maxL);
+    const int shape = shape_for_length(maxL);
     bool found = false;
     int best_dist = 1 << 30;
     std::string line;
     while (std::getline(f, line)) {
         std::istringstream is(line);
-        std::string a;
-        int l, v, wpb, pw, pers;
-        if (!(is >> a >> l >> v >> wpb >> pw >> pers))
+        std::string a, key;
+        int v, wpb, pw, pers;
+        if (!(is >> a >> key >> v >> wpb >> pw >> pers) || a != arch)
             continue;
-        if (a != arch || l < 3 || l > LABS_WALK_L_MAX || (l % 2) == 0 || shape_for_length(l) != shape)
-            continue;
-        const int dist = l > L ? l - L : L - l;
+        int dist = 0;
+        if (mixed) {
+            if (key != want)
+                continue;
+        } else {
+            if (key.empty() || key[0] == 'M')
+                continue;
+            const int l = atoi(key.c_str());
+            if (l < 3 || l > LABS_WALK_L_MAX || (l % 2) == 0 || shape_for_length(l) != shape)
+                continue;
+            dist = l > maxL ? l - maxL : maxL - l;
+        }
         if (dist <= best_dist) {
             best_dist = dist;
             o->variant = v;
@@ -890,7 +953,7 @@ static bool cache_lookup(int L, labs_plan_opts *o)
     return found;
 }
 
-static void cache_store(int L, const labs_plan_opts &o)
+static void cache_store(const std::string &key, const labs_plan_opts &o)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     const std::string path = cache_path();
@@ -902,7 +965,7 @@ static void cache_store(int L, const labs_plan_opts &o)
     std::ofstream f(path, std::ios::app);
     if (!f)
         return;
-    f << device_arch() << " " << L << " " << o.variant << " " << o.waves_per_block << " " << o.probe_width << " "
+    f << device_arch() << " " << key << " " << o.variant << " " << o.waves_per_block << " " << o.probe_width << " "
       << o.persistent << "\n";
 }
 
@@ -922,7 +985,7 @@ static int resolve_opts(labs_walk_plan *p, const labs_plan_opts *in)
         minL = std::min(minL, c.L);
     }
     labs_plan_opts tuned{};
-    const bool have = cache_lookup(maxL, &tuned);
+    const bool have = cache_lookup(minL, maxL, &tuned);
     // untuned default: the matrix-core scoring where it was measured faster (L >= 129),
     // the bit-sliced one elsewhere
     if (o.variant == LABS_VARIANT_AUTO)
@@ -978,32 +1041,21 @@ static int resolve_opts(labs_walk_plan *p, const labs_plan_opts *in)
 
 } // namespace liblabs
 
-extern "C" int labs_autotune(int32_t L, int32_t n_walks, labs_plan_opts *best)
+namespace liblabs {
+
+// Times every candidate launch form on the batch cfg (short synthetic runs: results never depend
+// on the form) and stores the fastest under key.
+static int tune_batch(const std::vector<labs_walk_cfg> &cfg, int maxL, const std::string &key,
+                      labs_plan_opts *best)
 {
-    if (L < 3 || L > LABS_WALK_L_MAX || (L % 2) == 0 || n_walks < 1)
-        return fail(LABS_EINVAL, "labs_autotune: L = %d, n_walks = %d", L, n_walks);
-    int rc = check_device();
-    if (rc)
-        return rc;
-    std::vector<labs_walk_cfg> cfg((size_t)n_walks);
-    for (int32_t i = 0; i < n_walks; i++) {
-        labs_walk_cfg &c = cfg[(size_t)i];
-        memset(&c, 0, sizeof c);
-        c.L = L;
-        c.table_log2 = 16;
-        c.seed = 0x7E57ull;
-        c.walk_id = (uint32_t)i;
-        c.steps = 512;
-        c.target_isl = -1;
-        c.watch_isl = -1;
-    }
+    const int32_t n_walks = (int32_t)cfg.size();
     struct Cand { labs_plan_opts o; };
     std::vector<Cand> cands;
     for (int v : {LABS_VARIANT_BITSLICE, LABS_VARIANT_DIRECT, LABS_VARIANT_MFMA})
         for (int wpb : {1, 2, 4})
             for (int pw : {1, 2})
                 for (int pers : {1, 2}) {
-                    if (v == LABS_VARIANT_MFMA && L > kMfmaLMax)
+                    if (v == LABS_VARIANT_MFMA && maxL > kMfmaLMax)
                         continue;
                     Cand c{};
                     c.o.variant = v;
@@ -1016,7 +1068,7 @@ extern "C" int labs_autotune(int32_t L, int32_t n_walks, labs_plan_opts *best)
     Cand winner = cands[0];
     for (const Cand &c : cands) {
         labs_walk_plan *p = nullptr;
-        rc = labs_walk_plan_create(n_walks, cfg.data(), &c.o, &p);
+        int rc = labs_walk_plan_create(n_walks, cfg.data(), &c.o, &p);
         if (rc)
             return rc;
         double total = 0.0;
@@ -1038,8 +1090,58 @@ extern "C" int labs_autotune(int32_t L, int32_t n_walks, labs_plan_opts *best)
             winner = c;
         }
     }
-    cache_store(L, winner.o);
+    cache_store(key, winner.o);
     if (best)
         *best = winner.o;
     return LABS_OK;
+}
+
+} // namespace liblabs
+
+extern "C" int labs_autotune(int32_t L, int32_t n_walks, labs_plan_opts *best)
+{
+    if (L < 3 || L > LABS_WALK_L_MAX || (L % 2) == 0 || n_walks < 1)
+        return fail(LABS_EINVAL, "labs_autotune: L = %d, n_walks = %d", L, n_walks);
+    int rc = check_device();
+    if (rc)
+        return rc;
+    std::vector<labs_walk_cfg> cfg((size_t)n_walks);
+    for (int32_t i = 0; i < n_walks; i++) {
+        labs_walk_cfg &c = cfg[(size_t)i];
+        memset(&c, 0, sizeof c);
+        c.L = L;
+        c.table_log2 = 16;
+        c.seed = 0x7E57ull;
+        c.walk_id = (uint32_t)i;
+        c.steps = 512;
+        c.target_isl = -1;
+        c.watch_isl = -1;
+    }
+    return tune_batch(cfg, L, batch_key(L, L), best);
+}
+
+extern "C" int labs_autotune_batch(int32_t n_walks, const labs_walk_cfg *cfg, labs_plan_opts *best)
+{
+    if (n_walks < 1 || !cfg)
+        return fail(LABS_EINVAL, "labs_autotune_batch: n_walks = %d with a cfg array required", n_walks);
+    int minL = 1 << 30, maxL = 0;
+    std::vector<labs_walk_cfg> tune((size_t)n_walks);
+    for (int32_t i = 0; i < n_walks; i++) {
+        int rc = walk_cfg_check(cfg[i], i);
+        if (rc)
+            return rc;
+        minL = std::min(minL, cfg[i].L);
+        maxL = std::max(maxL, cfg[i].L);
+        // the batch's walks, shortened to a sample of at most 512 steps, without traces or stops
+        labs_walk_cfg c = cfg[i];
+        c.flags = 0;
+        c.steps = std::min<int64_t>(c.steps, 512);
+        c.target_isl = -1;
+        c.watch_isl = -1;
+        tune[(size_t)i] = c;
+    }
+    int rc = check_device();
+    if (rc)
+        return rc;
+    return tune_batch(tune, maxL, batch_key(minL, maxL), best);
 }

@@ -74,25 +74,30 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// (the word operations of both sides add up whatever their minima)
 __device__ __forceinline__ void fold(EnumPartial &a, const EnumPartial &b)
 {
-    if (b.min_isl == 0xFFFFFFFFu)
-        return;
-    if (b.min_isl < a.min_isl) {
-        a = b;
-    } else if (b.min_isl == a.min_isl) {
-        a.count += b.count;
-        a.first_x = b.first_x < a.first_x ? b.first_x : a.first_x;
+    const uint64_t ops = a.word_ops + b.word_ops;
+    if (b.min_isl != 0xFFFFFFFFu) {
+        if (b.min_isl < a.min_isl) {
+            a = b;
+        } else if (b.min_isl == a.min_isl) {
+            a.count += b.count;
+            a.first_x = b.first_x < a.first_x ? b.first_x : a.first_x;
+        }
     }
+    a.word_ops = ops;
 }
 
-// Fold (best, cnt, first) of every thread of the block into part (read-modify-write: one slot
-// per block, the same block index on every launch of one enumeration).
-__device__ void block_merge(uint32_t best, uint32_t cnt, uint64_t first, EnumPartial *part)
+// Fold (best, cnt, first) of every thread of the block, and the word operations of its waves
+// (wave-uniform), into part (read-modify-write: one slot per block, the same block index on every
+// launch of one enumeration).
+__device__ void block_merge(uint32_t best, uint32_t cnt, uint64_t first, uint64_t ops, EnumPartial *part)
 {
     __shared__ uint32_t s_best[kEnumBlock / kWave];
     __shared__ uint32_t s_cnt[kEnumBlock / kWave];
     __shared__ uint64_t s_first[kEnumBlock / kWave];
+    __shared__ uint64_t s_ops[kEnumBlock / kWave];
     const uint32_t wb = wave_min_u32(best);
     const uint32_t wc = (uint32_t)wave_sum_i32(best == wb ? (int32_t)cnt : 0);
     const uint64_t wf = wave_min_u64(best == wb ? first : ~0ull);
@@ -101,6 +106,7 @@ __device__ void block_merge(uint32_t best, uint32_t cnt, uint64_t first, EnumPar
         s_best[wave] = wb;
         s_cnt[wave] = wc;
         s_first[wave] = wf;
+        s_ops[wave] = ops;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -111,6 +117,7 @@ __device__ void block_merge(uint32_t best, uint32_t cnt, uint64_t first, EnumPar
             w.reserved = 0;
             w.count = s_cnt[i];
             w.first_x = s_first[i];
+            w.word_ops = s_ops[i];
             fold(p, w);
         }
         part[blockIdx.x] = p;
@@ -137,6 +144,10 @@ __global__ void __launch_bounds__(kEnumBlock) k_enum_min(int L, uint64_t r_begin
 
     uint32_t best = 0xFFFFFFFFu, cnt = 0;
     uint64_t first = ~0ull;
+    // algorithmic word operations of the (sequence, lag) pairs this wave evaluates: 3 per word of
+    // the L - k overlapping positions (funnel shift, masked xor, popcount) and 2 for C_k^2, summed
+    // over the lags each pass actually runs (wave-uniform)
+    uint64_t ops = 0;
     // Pruning bound (wave-uniform): the lowest ISL any lane of the wave has found, and what this
     // block slot holds from earlier launches of the same enumeration.  Every C_k^2 >= 0, so a
     // partial sum above the bound is above the minimum: once every sequence of the wave's pass is
@@ -152,6 +163,10 @@ __global__ void __launch_bounds__(kEnumBlock) k_enum_min(int L, uint64_t r_begin
         const uint64_t g = g0 + lane_id();
         const bool valid = g < n_pass;
         const uint32_t bound = min(bound0, wave_min_u32(best));
+        // sequences of this wave pass inside the block (all of them but in the last passes)
+        uint32_t seqs = (uint32_t)(kWave * kEnumB);
+        if ((g0 + kWave) * kEnumB > r_count)
+            seqs = (uint32_t)wave_sum_i32(valid ? (int32_t)min<uint64_t>(kEnumB, r_count - g * kEnumB) : 0);
         uint32_t w[kEnumB][NW + 1];
         uint32_t isl[kEnumB];
 #pragma unroll
@@ -169,6 +184,7 @@ __global__ void __launch_bounds__(kEnumBlock) k_enum_min(int L, uint64_t r_begin
                 if (k >= L)
                     break;
                 const int len = L - k;
+                ops += (uint64_t)seqs * (uint64_t)(3 * ((len + 31) / 32) + 2);
                 uint32_t m[NW];
 #pragma unroll
                 for (int i = 0; i < NW; i++) {
@@ -220,7 +236,7 @@ __global__ void __launch_bounds__(kEnumBlock) k_enum_min(int L, uint64_t r_begin
             }
         }
     }
-    block_merge(best, cnt, first, part);
+    block_merge(best, cnt, first, ops, part);
 }
 
 __global__ void k_enum_part_init(EnumPartial *part, int count)
@@ -232,6 +248,7 @@ __global__ void k_enum_part_init(EnumPartial *part, int count)
         p.reserved = 0;
         p.count = 0;
         p.first_x = ~0ull;
+        p.word_ops = 0;
         part[i] = p;
     }
 }
@@ -246,6 +263,7 @@ __global__ void __launch_bounds__(kEnumBlock) k_enum_final(const EnumPartial *__
     acc.reserved = 0;
     acc.count = 0;
     acc.first_x = ~0ull;
+    acc.word_ops = 0;
     for (int i = (int)threadIdx.x; i < count; i += (int)blockDim.x)
         fold(acc, part[i]);
     s_p[threadIdx.x] = acc;

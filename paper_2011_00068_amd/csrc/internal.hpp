@@ -94,6 +94,9 @@ hipError_t launch_walk_general(int shape, WalkState *states, int32_t count, cons
 hipError_t launch_pq_walk(int shape, WalkState *states, int32_t count, const int32_t *order, uint64_t *tables,
                           uint64_t *nbr_tables, int nlog2, int cap, int32_t *trace, int32_t *scores,
                           hipStream_t stream);
+// first-improvement search with perturbations of P symbols (fi_walk.hip); no visited table
+hipError_t launch_fi_walk(int shape, WalkState *states, int32_t count, const int32_t *order, int P, int32_t *trace,
+                          int32_t *scores, hipStream_t stream);
 
 // Running result of one grouped skew-space minimum (one slot per block, then one final slot).
 struct EnumPartial {
@@ -101,6 +104,7 @@ struct EnumPartial {
     uint32_t reserved;
     uint64_t count;
     uint64_t first_x;
+    uint64_t word_ops; // algorithmic word operations of the (sequence, lag) pairs evaluated
 };
 int enum_min_blocks(int L);
 hipError_t launch_enum_part_init(EnumPartial *part, int count, hipStream_t stream);

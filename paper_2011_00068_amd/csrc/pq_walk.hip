@@ -202,6 +202,16 @@ __device__ __forceinline__ void run_pq(WalkState *__restrict__ wsp, uint64_t *__
         best_x[i] = w.x[i];
     int32_t hit = (tgt >= 0 && w.isl <= tgt) ? 0 : -1;
     int32_t wstep = (wch >= 0 && w.isl <= wch) ? 0 : -1;
+    // a restart state counts for the best like the initial state, occupied after iteration ts
+    auto note_start = [&](int32_t ts) {
+        if (w.isl < best32) {
+            best32 = w.isl;
+            best_step = ts;
+#pragma unroll
+            for (int i = 0; i < kXWords; i++)
+                best_x[i] = w.x[i];
+        }
+    };
 
     while (t < steps && !(tgt >= 0 && hit >= 0)) {
         asm volatile("" : "+v"(w.lane));
@@ -408,6 +418,7 @@ __device__ __forceinline__ void run_pq(WalkState *__restrict__ wsp, uint64_t *__
             restarts++;
             restart_idx++;
             start();
+            note_start(t + 1);
             move = -1;
         } else {
             if (e_gen == t) {
@@ -462,6 +473,11 @@ __device__ __forceinline__ void run_pq(WalkState *__restrict__ wsp, uint64_t *__
             restarts++;
             restart_idx++;
             start();
+            note_start(t);
+            if (tgt >= 0 && hit < 0 && best32 <= tgt)
+                hit = t;
+            if (wch >= 0 && wstep < 0 && best32 <= wch)
+                wstep = t;
         }
     }
 

@@ -334,9 +334,9 @@ extern "C" int labs_search_submit(labs_server *S, const labs_search_req *r, uint
     j.steps = r->flip_budget / ((int64_t)r->n_walks * j.n);
     j.isl_t = -1;
     if (r->target_F_num > 0) {
-        // F >= num/den  <=>  L^2 / (2 ISL) >= num/den  <=>  ISL <= L^2 den / (2 num)
-        const __int128 v = (__int128)r->L * r->L * r->target_F_den / ((__int128)2 * r->target_F_num);
-        j.isl_t = (int64_t)std::min<__int128>(v, (__int128)INT64_MAX);
+        const int rc = labs_isl_threshold(r->L, r->target_F_num, r->target_F_den, &j.isl_t);
+        if (rc)
+            return rc;
     }
     std::unique_lock<std::mutex> lk(S->mu);
     if (S->device_error)

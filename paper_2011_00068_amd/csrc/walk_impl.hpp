@@ -661,7 +661,34 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
         bk[4] = hit_found0;
         bk[5] = watch_found0;
     }
-    // steps of this launch at which best / hit / watch were reached (-1 = not in this launch)
+    // A state occupied after step ts of this launch with ISL <= thr: update best / hit / watch
+    // (uniform updates first, then one lane-0 store block, so that thr and lim stay scalar).
+    // Committed states and restart states alike (a restart is the walk's initialisation again).
+    auto note_state = [&](int32_t ts_at) {
+        int32_t best = su(bk[0]);
+        int32_t hf = su(bk[4]), wf = su(bk[5]);
+        const bool nb = w.isl < best;
+        const bool nh = tgt >= 0 && !hf && w.isl <= tgt;
+        const bool nw = wch >= 0 && !wf && w.isl <= wch;
+        best = nb ? w.isl : best;
+        hf |= nh ? 1 : 0;
+        wf |= nw ? 1 : 0;
+        lim = nh ? -1 : lim;
+        thr = su(threshold(best, hf != 0, wf != 0));
+        if (nb && w.lane < kXWords)
+            bl[w.lane] = xl[w.lane];
+        if (w.lane == 0) {
+            bk[0] = best;
+            if (nb)
+                bk[1] = ts_at;
+            if (nh)
+                bk[2] = ts_at;
+            if (nw)
+                bk[3] = ts_at;
+            bk[4] = hf;
+            bk[5] = wf;
+        }
+    };
     // steps left before the budget, as seen from this launch (periodic restarts stop there)
     const int32_t left32 = (int32_t)min<int64_t>(steps - t0, INT32_MAX);
     int32_t *trp = (TRACE && trace_off >= 0) ? trace + 2 * (trace_off + t0) : nullptr;
@@ -694,6 +721,9 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
                 trap_trp[1] = w.isl;
             }
             trap_trp = nullptr;
+            lds_fence(); // the new free bits in LDS before note_state copies them
+            if (w.isl <= thr)
+                note_state(ts);
         }
         while (ts < lim) {
             // Keep per-lane index arithmetic inside the loop instead of pinning ~100 VGPRs of
@@ -799,33 +829,8 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
             }
             if (TRACE && scp)
                 scp += n;
-            if (w.isl <= thr) {
-                // uniform updates first, then one lane-0 store block (so that thr and lim stay
-                // scalar)
-                int32_t best = su(bk[0]);
-                int32_t hf = su(bk[4]), wf = su(bk[5]);
-                const bool nb = w.isl < best;
-                const bool nh = tgt >= 0 && !hf && w.isl <= tgt;
-                const bool nw = wch >= 0 && !wf && w.isl <= wch;
-                best = nb ? w.isl : best;
-                hf |= nh ? 1 : 0;
-                wf |= nw ? 1 : 0;
-                lim = nh ? -1 : lim;
-                thr = su(threshold(best, hf != 0, wf != 0));
-                if (nb && w.lane < kXWords)
-                    bl[w.lane] = xl[w.lane];
-                if (w.lane == 0) {
-                    bk[0] = best;
-                    if (nb)
-                        bk[1] = ts;
-                    if (nh)
-                        bk[2] = ts;
-                    if (nw)
-                        bk[3] = ts;
-                    bk[4] = hf;
-                    bk[5] = wf;
-                }
-            }
+            if (w.isl <= thr)
+                note_state(ts);
             if (rem == 0) {
                 rem = R32;
                 // periodic restart (not after the last step, not once stopped)

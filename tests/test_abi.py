@@ -43,3 +43,40 @@ def test_strerror_without_device():
     lib.labs_strerror.restype = ctypes.c_char_p
     assert lib.labs_strerror(0) == b"ok"
     assert lib.labs_strerror(-2) == b"sequence is not skew-symmetric"
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="liblabs.so not built")
+def test_isl_threshold_through_the_abi():
+    """labs_isl_threshold (Eq. (3)): F >= num/den <=> ISL <= floor(L^2 den / (2 num)).  Host
+    arithmetic, so it runs without a GPU.  Checked on the F >= 8 and F >= 8.5 bounds at the ends and
+    middle of Table 1's range and, for random arguments, by the defining inequalities of the floor
+    (never by re-evaluating the same formula)."""
+    import random
+
+    lib = ctypes.CDLL(LIB)
+    f = lib.labs_isl_threshold
+    f.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    out = ctypes.c_int64()
+
+    def thr(L, num, den):
+        rc = f(L, num, den, ctypes.byref(out))
+        return rc, out.value
+
+    # F = L^2 / (2 ISL): the largest ISL with F >= 8 is floor(L^2 / 16), with F >= 8.5 floor(L^2 / 17)
+    for L, f8, f85 in ((201, 2525, 2376), (255, 4064, 3825), (303, 5738, 5400)):
+        assert thr(L, 8, 1) == (0, f8)
+        assert thr(L, 17, 2) == (0, f85)
+        assert L * L / (2 * f8) >= 8.0 > L * L / (2 * (f8 + 1))
+    rng = random.Random(2011000068)
+    for _ in range(2000):
+        L = rng.randint(1, 65535)
+        num = rng.randint(1, 10 ** 6)
+        den = rng.randint(1, 10 ** 6)
+        rc, t = thr(L, num, den)
+        assert rc == 0
+        # t is the largest integer with 2 num t <= L^2 den
+        assert 2 * num * t <= L * L * den < 2 * num * (t + 1)
+    assert thr(255, 1, 1 << 62) == (0, (1 << 63) - 1)  # clamped
+    for bad in ((0, 8, 1), (65536, 8, 1), (255, 0, 1), (255, 8, 0), (255, -1, 1)):
+        assert thr(*bad)[0] == -1, bad
+    assert f(255, 8, 1, None) == -1

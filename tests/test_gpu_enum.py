@@ -97,3 +97,23 @@ def test_empty_and_bad_blocks(labs):
         with pytest.raises(labs.LabsError) as e:
             labs.enum_skew_min(*args)
         assert e.value.code == labs.LABS_EINVAL
+
+
+def _exhaustive_word_ops(L, sequences):
+    # 3 word operations per 32-bit word of the L - k overlapping positions and 2 for C_k^2, per
+    # even lag k, for every sequence scored (one per group of four)
+    return sequences * sum(3 * ((L - k + 31) // 32) + 2 for k in range(2, L, 2))
+
+
+@pytest.mark.parametrize("L", [13, 31, 61])
+def test_word_ops_count(labs, L):
+    # the branch and bound evaluates at most the exhaustive count of (sequence, lag) pairs and at
+    # least every lag of one sequence per wave pass of 8 groups per lane; a block of one group
+    # scores exactly one sequence at every lag (nothing to compare it with, so no cut)
+    n = (L + 1) // 2
+    groups = 1 << (n - 2)
+    g = labs.enum_skew_min(L)
+    assert 0 < g["word_ops"] <= _exhaustive_word_ops(L, groups)
+    one = labs.enum_skew_min(L, groups // 3, groups // 3 + 1)
+    assert one["word_ops"] == _exhaustive_word_ops(L, 1)
+    assert labs.enum_skew_min(L, 5, 5)["word_ops"] == 0

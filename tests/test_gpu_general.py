@@ -130,3 +130,18 @@ def test_rejects_bad_config(labs):
         with pytest.raises(labs.LabsError) as e:
             labs.general_walk_batch([labs.make_cfg(**kw)])
         assert e.value.code == labs.LABS_EINVAL
+
+
+def test_restart_states_count(labs):
+    # general walks restarting after every step (and trapping at L = 4): restart states count for
+    # the best, hit and watch like the initial state
+    cfgs = []
+    for w in range(6):
+        ref = o.walk(12, SEED, w, steps=40, restart_period=1, table_log2=13, general=True)
+        cfgs.append(labs.make_cfg(12, SEED, w, steps=40, restart_period=1, table_log2=13, trace=True))
+        cfgs.append(labs.make_cfg(12, SEED, w, steps=40, restart_period=1, table_log2=13,
+                                  watch_isl=ref["best_isl"], target_isl=ref["best_isl"], trace=True))
+    cfgs.append(labs.make_cfg(4, SEED, 5, steps=50, table_log2=8, trace=True))
+    got, _ = labs.general_walk_batch(cfgs)
+    for i, c in enumerate(cfgs):
+        assert_same(got[i], oracle_general(c), i)

@@ -110,3 +110,19 @@ def test_rejects_bad_options(labs):
     with pytest.raises(labs.LabsError) as e:
         labs.pq_walk_batch([labs.make_cfg(31, 1, 0, steps=1 << 31, table_log2=16)], 4)
     assert e.value.code == labs.LABS_EINVAL
+
+
+def test_restart_states_count(labs):
+    # a restart every iteration (and every trap) at short lengths: restart states count for the
+    # best, hit and watch like the initial state, at the iteration after which they are occupied
+    cfgs = []
+    for w in range(6):
+        cfgs.append(labs.make_cfg(21, SEED, w, steps=40, restart_period=1, table_log2=12, trace=True))
+        ref = o.walk(21, SEED, w, steps=40, restart_period=1, table_log2=12, pq_capacity=3)
+        cfgs.append(labs.make_cfg(21, SEED, w, steps=40, restart_period=2, table_log2=12,
+                                  watch_isl=ref["best_isl"], target_isl=ref["best_isl"] + 8, trace=True))
+    cfgs.append(labs.make_cfg(5, SEED, 4, steps=60, table_log2=8, trace=True))
+    for Q, nlog2 in ((1, 0), (3, 0), (8, 5)):
+        got, _ = labs.pq_walk_batch(cfgs, Q, nlog2)
+        for i, c in enumerate(cfgs):
+            assert_same(got[i], oracle_pq(c, Q, nlog2), (i, Q, nlog2))

@@ -81,6 +81,24 @@ def test_single_job_stops_at_tick_after_hit(labs):
     assert job_view(labs, st, L) == want
 
 
+def test_served_long_jobs_match_oracle(labs):
+    # jobs at the serving workload's lengths (L >= 201, the matrix-core kernel the server runs
+    # there): one without a target, one stopping at the first tick boundary after an F >= 5 hit
+    srv = labs.Server(device_mem_bytes=64 * PER_WALK_BYTES, table_log2=TABLE_LOG2, steps_per_tick=128)
+    reqs = [(303, 3, SEED + 5, 3 * 152 * 900, None), (201, 4, SEED + 6, 4 * 101 * 1500, (5, 1))]
+    ids = [srv.submit(L, W, seed, budget, target_F=tf) for L, W, seed, budget, tf in reqs]
+    got = [srv.wait(j, timeout_ms=120000) for j in ids]
+    srv.close()
+    for (L, W, seed, budget, tf), (done, st) in zip(reqs, got):
+        assert done and st["state"] == labs.JOB_DONE
+        n = (L + 1) // 2
+        isl_t = labs.isl_threshold(L, *tf) if tf else -1
+        want = oracle_job(L, W, seed, budget // (W * n), isl_t, 128)
+        if tf:
+            assert 0 <= want["hit_step"] < budget // (W * n)
+        assert job_view(labs, st, L) == want, (L, job_view(labs, st, L), want)
+
+
 def test_alone_equals_mix(labs):
     # the same request alone, and submitted while other jobs of other lengths come and go
     req = (101, 5, 777, 5 * 51 * 700, (9, 2))
@@ -91,24 +109,32 @@ def test_alone_equals_mix(labs):
 
     srv = labs.Server(device_mem_bytes=40 * PER_WALK_BYTES, table_log2=TABLE_LOG2, steps_per_tick=50)
     rng = random.Random(5)
-    others = []
+    others = []  # (request, job id)
     for i in range(4):
-        L = rng.choice([33, 63, 201, 255])
-        others.append(srv.submit(L, rng.randint(3, 12), 100 + i, rng.randint(1, 4) * 20000, target_F=(6, 1)))
+        r = (rng.choice([33, 63, 201, 255]), rng.randint(3, 12), 100 + i, rng.randint(1, 4) * 20000, (6, 1))
+        others.append((r, srv.submit(*r[:4], target_F=r[4])))
     time.sleep(0.01)
     jid = srv.submit(*req[:4], target_F=req[4])
     for i in range(4):
-        L = rng.choice([101, 301])
-        others.append(srv.submit(L, rng.randint(2, 9), 200 + i, 60000))
+        r = (rng.choice([101, 301]), rng.randint(2, 9), 200 + i, 60000, None)
+        others.append((r, srv.submit(*r[:4], target_F=r[4])))
     _, mixed = srv.wait(jid, timeout_ms=120000)
-    for j in others:
-        done, _ = srv.wait(j, timeout_ms=120000)
-        assert done
+    co = []
+    for r, j in others:
+        done, st = srv.wait(j, timeout_ms=120000)
+        assert done and st["state"] == labs.JOB_DONE
+        co.append(st)
     stats = srv.stats()
     srv.close()
     assert stats["peak_walks"] <= 40
     assert job_view(labs, alone, 101) == job_view(labs, mixed, 101)
     assert alone["state"] == mixed["state"] == labs.JOB_DONE
+    # every co-scheduled job (L = 33 .. 301, with and without a target) is its request's result
+    # alone: the oracle's walks cut at the job's stopping tick
+    for (L, W, seed, budget, tf), st in zip((r for r, _ in others), co):
+        n = (L + 1) // 2
+        isl_t = labs.isl_threshold(L, *tf) if tf else -1
+        assert job_view(labs, st, L) == oracle_job(L, W, seed, budget // (W * n), isl_t, 50), (L, W, seed)
 
 
 def test_admission_by_memory_and_cancel(labs):

@@ -207,7 +207,7 @@ def test_mfma_launch_options_and_mixed_lengths(labs):
 
 def test_l255_headline_full_size(labs):
     # the L = 255 headline workload exactly as bench.py runs it (16,384 walks x 4,768 steps, restart
-    # period 2^20, stop at F >= 8.5, watch F >= 8): sampled walks against the oracle, properties on
+    # period 2^20, stop at F >= 8.5, watch F >= 5): sampled walks against the oracle, properties on
     # a stride of the rest
     import bench
 
@@ -250,3 +250,42 @@ def test_walk_rejects_bad_config(labs):
         with pytest.raises(labs.LabsError) as e:
             labs.WalkPlan([c])
         assert e.value.code == labs.LABS_EINVAL
+
+
+def _restart_state_cases(labs, traced):
+    # walks restarting after every step at L = 21 (exact table) whose best is a restart state, and
+    # watch / target levels first met by a restart state (found with the oracle)
+    L, S, n = 21, 40, 11
+    cfgs = []
+    for w in range(300):
+        r = o.walk(L, SEED, w, steps=S, restart_period=1, table_log2=n + 1, trace=True)
+        starts = {o.start_bits(L, SEED, w, k): k for k in range(1, S)}
+        if r["best_bits"] in starts and r["best_step"] == starts[r["best_bits"]]:
+            cfgs.append(labs.make_cfg(L, SEED, w, steps=S, restart_period=1, table_log2=n + 1, trace=traced))
+            lvl = r["best_isl"]
+            cfgs.append(labs.make_cfg(L, SEED, w, steps=S, restart_period=1, table_log2=n + 1, watch_isl=lvl,
+                                      trace=traced))
+            cfgs.append(labs.make_cfg(L, SEED, w, steps=S, restart_period=1, table_log2=n + 1, target_isl=lvl,
+                                      trace=traced))
+        if len(cfgs) >= 12:
+            break
+    assert len(cfgs) >= 6
+    # traps (L = 5, exact table) and periodic restarts at the matrix-core lengths
+    cfgs.append(labs.make_cfg(5, SEED, 3, steps=50, table_log2=8, trace=traced))
+    cfgs.append(labs.make_cfg(255, SEED, 6, steps=30, restart_period=1, table_log2=10, trace=traced))
+    return cfgs
+
+
+@pytest.mark.parametrize("traced", [True, False], ids=["traced", "untraced"])
+def test_restart_states_count_for_best_hit_watch(labs, traced):
+    cfgs = _restart_state_cases(labs, traced)
+    for variant in (1, 2, 3):
+        for opt in (dict(), dict(steps_per_launch=7)):
+            plan = labs.WalkPlan(cfgs, variant=variant, **opt)
+            plan.run()
+            res = plan.results()
+            plan.close()
+            for i, c in enumerate(cfgs):
+                assert_same(res[i], oracle_walk(c, trace=traced), (i, variant, opt))
+    # some of them stop at a target met by a restart state
+    assert any(c.target_isl >= 0 for c in cfgs)

@@ -70,3 +70,30 @@ def test_uneven_batch_full_size(labs):
     for c, r in zip(short, rs):
         ref = o.walk(c.L, SEED, 0, steps=300, table_log2=16, trace=True)
         assert np.array_equal(r["trace"], ref["trace"])
+
+
+def test_uneven_batch_long_walks_match_oracle(labs):
+    # The uneven batch's launch (all 52 lengths x 64 walks in one grid of the mixed-length
+    # matrix-core kernel, replayed from a hipGraph) run for 2 x 10^5 steps, past the point where
+    # the 2^16-word visited tables start to evict; three of its walks (shortest, headline and
+    # longest length) compared with the oracle in every result field.
+    from concurrent.futures import ThreadPoolExecutor
+
+    steps = 200000
+    lengths = list(range(201, 304, 2))
+    cfgs = [labs.make_cfg(L, SEED, w, steps=steps, table_log2=16) for L in lengths for w in range(64)]
+    plan = labs.WalkPlan(cfgs, use_graph=True)
+    assert plan.opts()["variant"] == labs.VARIANT_MFMA
+    plan.run()
+    res = plan.results()
+    _, launches = plan.last_timing()
+    plan.close()
+    assert launches == 1
+    picks = [(201, 0), (255, 17), (303, 63)]
+    with ThreadPoolExecutor(max_workers=len(picks)) as ex:
+        refs = list(ex.map(lambda p: o.walk(p[0], SEED, p[1], steps=steps, table_log2=16), picks))
+    for (L, w), ref in zip(picks, refs):
+        got = res[lengths.index(L) * 64 + w]
+        for k in ("best_isl", "best_step", "steps_done", "flip_evals", "hit_step", "watch_step", "final_isl",
+                  "restarts", "traps", "best_bits", "final_bits"):
+            assert got[k] == ref[k], (L, w, k, got[k], ref[k])
