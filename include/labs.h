@@ -131,6 +131,19 @@ typedef struct labs_enum_min_result {
 int labs_enum_skew_min(int32_t L, uint64_t r_begin, uint64_t r_end, labs_enum_min_result *out,
                        void *stream);
 
+/* labs_enum_skew_min for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same arguments and results, except
+ * kernel_ms = -1 (not timed: timing would create events).  It calls no hipMalloc, hipFree or other
+ * allocating routine: its per-block partial results live in a fixed device array of 4096 slots of
+ * 32 bytes (128 KiB) that each GPU the library runs on holds from the first call on it until the
+ * process ends (a device with more than 4095 resident enumeration blocks runs a smaller grid; the
+ * results do not depend on the grid).  Every call clears the slots it uses before it starts, so
+ * nothing carries over between calls, but all calls on one GPU share the array: calls that
+ * overlap in time on one GPU (from several threads or streams) race and must not be made.
+ * Blocking on `stream`.  Errors as labs_enum_skew_min. */
+int labs_enum_skew_min_noalloc(int32_t L, uint64_t r_begin, uint64_t r_end, labs_enum_min_result *out,
+                               void *stream);
+
 /* ---------------------------------------------------------------------------------------------
  * One-flip evaluation (Section 3; Algorithm 1's fast merit-factor step).
  * ------------------------------------------------------------------------------------------- */

@@ -43,6 +43,7 @@ JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_CANCELLED = 0, 1, 2, 3
 EXPORTS = [
     "labs_strerror", "labs_last_error", "labs_device_info", "labs_probe_lds_read",
     "labs_isl", "labs_merit", "labs_isl_threshold", "labs_isl_batch_dev", "labs_enum_skew_dev", "labs_enum_skew_min",
+    "labs_enum_skew_min_noalloc",
     "labs_flip_scores_dev",
     "labs_walk_batch", "labs_walk_plan_create", "labs_walk_plan_run", "labs_walk_plan_results",
     "labs_walk_plan_get_opts", "labs_walk_plan_last_timing", "labs_walk_plan_destroy",
@@ -194,6 +195,7 @@ def lib():
     L.labs_isl_batch_dev.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp]
     L.labs_enum_skew_dev.argtypes = [i32, vp, vp]
     L.labs_enum_skew_min.argtypes = [i32, u64, u64, P(EnumMinResult), vp]
+    L.labs_enum_skew_min_noalloc.argtypes = [i32, u64, u64, P(EnumMinResult), vp]
     L.labs_flip_scores_dev.argtypes = [i32, i32, vp, vp, i32, vp]
     L.labs_walk_batch.argtypes = [i32, P(WalkCfg), P(WalkResult), vp, vp, vp]
     L.labs_walk_plan_create.argtypes = [i32, P(WalkCfg), P(PlanOpts), P(vp)]
@@ -307,6 +309,18 @@ def enum_skew_min(L, r_begin=0, r_end=None):
         r_end = 1 << max(0, n - 2)
     res = EnumMinResult()
     _check(lib().labs_enum_skew_min(L, r_begin, r_end, ctypes.byref(res), _stream()), "labs_enum_skew_min")
+    return {"min_isl": res.min_isl, "count": res.count, "first_x": res.first_x, "states": res.states,
+            "kernel_ms": res.kernel_ms, "word_ops": res.word_ops}
+
+
+def enum_skew_min_noalloc(L, r_begin=0, r_end=None):
+    """enum_skew_min through labs_enum_skew_min_noalloc (no device allocation; kernel_ms = -1)."""
+    n = (L + 1) // 2
+    if r_end is None:
+        r_end = 1 << max(0, n - 2)
+    res = EnumMinResult()
+    _check(lib().labs_enum_skew_min_noalloc(L, r_begin, r_end, ctypes.byref(res), _stream()),
+           "labs_enum_skew_min_noalloc")
     return {"min_isl": res.min_isl, "count": res.count, "first_x": res.first_x, "states": res.states,
             "kernel_ms": res.kernel_ms, "word_ops": res.word_ops}
 
