@@ -31,9 +31,19 @@
 // register r of lane l is D[4 (l / 16) + r][l % 16]; so lane l receives Y_j, Y_{j+1} for h = l
 // and Z for h = 63 - l, which one ds_bpermute brings to lane h.
 //
-// Lane l owns flips j = 2 l and 2 l + 1 (the same h, both parities), so the two flips share their
-// window offsets.  The correlation table is lane-held as in the bit-sliced walker, and so are the
-// parity bit strings and the commit.
+// Lane l owns flips j = 2 l and 2 l + 1 (the same h, both parities).  The correlation table is
+// lane-held as in the bit-sliced walker.
+//
+// rc'_j is kept per owned flip across commits instead of being recounted every step.  Committing
+// js (negating s_js and its mirror m' = 2c - js, where s_m' = (-1)^(c-js) s_js) toggles whether
+// p and q differ in at most two terms s_{j+k} s_{j-k} of flip j, and only for j of the parity of
+// js: the term with end js (partner 2 j - js; not counted when that partner is the mirror of j,
+// the excluded shift) and the term with end m' (partner 2 j - m'; the same term when js = c).
+// A term whose ends were equal now differs and the reverse, so for j < c, j != js
+//   d rc'_j = s_js (s_{2j-js} + (-1)^(c-js) [js != c] s_{2j-m'}),
+// with s taken before the commit and 0 outside the sequence (the partners are never js or m').
+// The parity bit strings are then read only when a walk (re)starts, so commits no longer update
+// them.
 #pragma once
 
 #include "walk_impl.hpp"
@@ -51,9 +61,13 @@ typedef __attribute__((address_space(3))) const mfma_v4i lds_cv4;  // 16-byte al
 // The A operand of a tile is one 16-byte read per lane.  The 16 lanes of a row group read kinds
 // 0..3 x 4 windows of 16 bytes at the same K offset, so the strings that one tile reads must sit
 // at distinct multiples of 16 dwords modulo 64 for the group to cover 64 distinct banks.  Small
-// layout: strings 80 dwords apart (0, 16, 32, 48 mod 64).  Big layout: strings 0..3 144 apart
-// (0, 16, 32, 48), then strings 4 and 5 (the second tile's kinds 2/3, read beside kinds 0/1 at
-// +16 dwords, i.e. 16 and 32 mod 64) at 0 and 48 mod 64.
+// layout: strings 80 dwords apart from dword 16 (16, 32, 48, 0 mod 64).  Big layout: strings 0..3
+// 144 apart from dword 32 (32, 48, 0, 16), then strings 4 and 5 (the second tile's kinds 2/3,
+// read beside kinds 0/1 at +16 dwords, i.e. 48 and 0 mod 64) at 32 and 16 mod 64.
+//
+// The rc' update of a commit reads s^p at half indices down to -63 (small) / -95 (big) from the
+// kind-p strings: zero words before string 0 (the first 16 / 32 dwords of sbuf) and the gap
+// between strings 0 and 1 (16 / 52 dwords) are kept zero for it.
 template <int NSTR, int SEQ_DWORDS, int C_DWORDS, int C_WORDS>
 struct alignas(16) WaveLdsMfmaT {
     static constexpr int kStrings = NSTR;
@@ -63,13 +77,17 @@ struct alignas(16) WaveLdsMfmaT {
     // dword offset of string k in sbuf
     __host__ __device__ static constexpr int str_off(int k)
     {
-        return NSTR == 4 ? 80 * k : (k < 4 ? 144 * k : 576 + 112 * (k - 4));
+        return NSTR == 4 ? 16 + 80 * k : 32 + (k < 4 ? 144 * k : 576 + 112 * (k - 4));
     }
     static constexpr int kSbufDwords = str_off(NSTR - 1) + SEQ_DWORDS;
     static_assert(NSTR == 4 || NSTR == 6, "four or six strings");
     static_assert(NSTR == 4 ? (80 >= SEQ_DWORDS) : (144 >= SEQ_DWORDS && 112 >= SEQ_DWORDS &&
                                                     576 >= 3 * 144 + SEQ_DWORDS),
                   "strings overlap");
+    // zero bytes before the kind-p strings (string 0: the leading pad; string 1: the gap)
+    static_assert(4 * str_off(0) >= (NSTR == 4 ? 63 : 95) &&
+                      4 * (str_off(1) - str_off(0) - SEQ_DWORDS) >= (NSTR == 4 ? 63 : 95),
+                  "zero pads of the rc' reads");
     uint32_t par[2][kParWords];       // bit a of par[p] = b_{2a+p} (0 past the sequence end)
     uint32_t rev[2][kRevWords];       // bit a of rev[p] = bit (kNA-1-a) of par[p], 0 past kNA-1
     uint32_t xw[kXWords];             // free bits (kept current by every commit)
@@ -90,6 +108,17 @@ using WaveLdsMfmaBig = WaveLdsMfmaT<6, 92, 74, 192>;
 static_assert(offsetof(WaveLdsMfma, sbuf) % 16 == 0 && offsetof(WaveLdsMfmaBig, sbuf) % 16 == 0,
               "strings 16-byte aligned");
 
+// v in every lane but lane b (a uniform index; no lane when b is outside 0..63, unless IN_RANGE
+// promises 0 <= b < 64), 0 in lane b: one v_cndmask with the lane mask built on the scalar unit
+template <bool IN_RANGE>
+__device__ __forceinline__ int32_t drop_lane(int b, int32_t v)
+{
+    const uint64_t keep = IN_RANGE ? ~(1ull << b) : ((b >= 0 && b < 64) ? ~(1ull << b) : ~0ull);
+    int32_t r;
+    asm("v_cndmask_b32_e64 %0, 0, %1, %2" : "=v"(r) : "v"(v), "s"(keep));
+    return r;
+}
+
 __device__ __forceinline__ uint32_t nibble_bytes(uint32_t nib)
 {
     // 4 bits -> 4 bytes of 0/1 (the shifted copies never overlap, so the product has no carries)
@@ -99,8 +128,9 @@ __device__ __forceinline__ uint32_t nibble_bytes(uint32_t nib)
 // Per-lane constants of one owned flip (they depend only on L and j).
 struct MfmaFlip {
     const int32_t *c_kd; // C'_{kappa_d}; the zero word C'_c for the centre (and past it)
-    uint32_t m0, m1, m2; // both-sided shifts but kappa_d: bits kappa < nq, kappa != kappa_d
     int32_t hc;          // np + 3 nq - 1 - 2 [q_d valid]; nq for the centre
+    int32_t rcf;         // factor of rc'_j: -64 for j < c, 0 for the centre and past it (whose rc
+                         // the commits do not keep)
 };
 
 // KW: shift window words (c <= 32 KW); BIG: flips up to c = 191 (two tiles, four flips per
@@ -124,6 +154,7 @@ struct MfmaWalker {
     uint32_t x[kXWords]; // free bits; current only where commit<true> is used (else in lds->xw)
     uint32_t x0;         // free bits 0..31, always current
     int32_t Cv[QR];
+    int32_t rc[G];       // rc'_j of the owned flips (0 for j >= c), kept across commits
     int32_t mult[G];     // factor of T_j: -8 s_j (-4 s_c for the centre, 0 past it)
     int planes;
     int32_t eps8[2];     // 8 (-1)^(c-j) for j of parity 0 / 1 (uniform)
@@ -132,7 +163,6 @@ struct MfmaWalker {
     MfmaFlip fc[G];
     uint32_t ta, tb;   // LDS addresses of this lane's A and B words of K block 0 (see init_lanes())
     uint32_t ta2;      // the same for the second tile's A operand (BIG)
-    uint32_t wpa, wqa; // LDS addresses of the first window words of par[0] and rev[0] (see score())
     int32_t bsrc;      // ds_bpermute source of Z: lane 63 - lane
 
     __device__ __forceinline__ int flip(int g) const { return (g < 2 ? 0 : 128) + 2 * lane + (g & 1); }
@@ -164,13 +194,9 @@ struct MfmaWalker {
             ta = (uint32_t)(uintptr_t)(lds->str(kind) + 4 * (slice + ib));
             ta2 = BIG ? (uint32_t)(uintptr_t)(lds->str(kind < 2 ? kind : kind + 2) + 4 * (slice + ib) + (kind < 2 ? 16 : 0)) : 0u;
             tb = (uint32_t)(uintptr_t)&lds->cb[r][(16 * slice - 1 - nn + 20 - r) >> 2];
-            // window words of the both-sided shifts kappa < nq (nq = ln, or 64 + ln): the p window
-            // starts at bit h+1 of par[g], the q window at bit kNA-h of rev[g]
-            wpa = (uint32_t)(uintptr_t)&lds->par[0][(ln + 1) >> 5];
-            wqa = (uint32_t)(uintptr_t)&lds->rev[0][(kNA - ln) >> 5];
             bsrc = (63 - ln) << 2;
             // whole addresses, so that every load is one base register plus an offset
-            asm volatile("" : "+v"(ta), "+v"(tb), "+v"(wpa), "+v"(wqa), "+v"(bsrc));
+            asm volatile("" : "+v"(ta), "+v"(tb), "+v"(bsrc));
             if constexpr (BIG)
                 asm volatile("" : "+v"(ta2));
         }
@@ -183,21 +209,13 @@ struct MfmaWalker {
             if (j < c) {
                 const int kd = c - 1 - j; // <= 62 for the second tile's flips
                 const bool qdv = kd < nq;
-                // bits kappa < nq (nq <= 63, or 64 <= nq <= 95 in the second tile)
-                uint64_t m = g < 2 ? (1ull << nq) - 1ull : ~0ull;
-                if (qdv)
-                    m &= ~(1ull << kd);
                 f.c_kd = &lds->C[kd];
-                f.m0 = (uint32_t)m;
-                f.m1 = (uint32_t)(m >> 32);
-                f.m2 = g < 2 ? 0u : (1u << (nq - 64)) - 1u;
                 f.hc = np + 3 * nq - 1 - (qdv ? 2 : 0);
+                f.rcf = -64;
             } else {
                 f.c_kd = &lds->C[c];
-                f.m0 = 0u;
-                f.m1 = 0u;
-                f.m2 = 0u;
                 f.hc = nq;
+                f.rcf = 0;
             }
         }
     }
@@ -243,6 +261,11 @@ struct MfmaWalker {
             lds->rev[lane & 1][6 + (lane >> 1)] = 0u;
         for (int i = lane; i < 4 * LdsT::kCDwords; i += kWave)
             lds->cb[i / LdsT::kCDwords][i % LdsT::kCDwords] = 0u;
+        // the zero pads before the kind-p strings
+        for (int i = lane; i < LdsT::str_off(0); i += kWave)
+            lds->sbuf[i] = 0u;
+        for (int i = LdsT::str_off(0) + LdsT::kSeqDwords + lane; i < LdsT::str_off(1); i += kWave)
+            lds->sbuf[i] = 0u;
         // prepare() writes C'_kappa for kappa < 64 QR; the zero word C'_c may lie past that (c = 64)
         for (int i = lane; i < LdsT::kCWords; i += kWave)
             lds->C[i] = 0;
@@ -310,7 +333,49 @@ struct MfmaWalker {
                 hz ^= zk[j];
         }
         h = wave_xor_u64(hz);
+        init_rc();
         lds_fence();
+    }
+
+    // rc'_j of the owned flips from the parity bit strings (a walk's start and every launch's
+    // resume): the number of both-sided shifts kappa < nq, kappa != kappa_d, at which the p window
+    // (bits h+1 .. of par[p]) and the q window (bits kNA-h .. of rev[p]) differ.
+    __device__ __forceinline__ void init_rc()
+    {
+        const int lane = this->lane;
+        const uint32_t sp = (uint32_t)(lane + 1); // window shifts: h+1 and kNA-h = 1 - sp (mod 32)
+        const uint32_t *wp = &lds->par[0][(lane + 1) >> 5];
+        const uint32_t *wq = &lds->rev[0][(kNA - lane) >> 5];
+#pragma unroll
+        for (int g = 0; g < G; g++) {
+            const int j = flip(g);
+            const int nq = j >> 1;
+            uint32_t m0 = 0u, m1 = 0u, m2 = 0u;
+            if (j < c) {
+                const int kd = c - 1 - j;
+                // bits kappa < nq (nq <= 63, or 64 <= nq <= 95 in the second tile)
+                uint64_t m = g < 2 ? (1ull << nq) - 1ull : ~0ull;
+                if (kd < nq)
+                    m &= ~(1ull << kd);
+                m0 = (uint32_t)m;
+                m1 = (uint32_t)(m >> 32);
+                m2 = g < 2 ? 0u : (1u << (nq - 64)) - 1u;
+            }
+            // the second tile's windows start 64 bits further in par, 64 bits earlier in rev
+            const uint32_t *wpg = wp + (g & 1) * kParWords + (g < 2 ? 0 : 2);
+            const uint32_t *wqg = wq + (g & 1) * kRevWords - (g < 2 ? 0 : 2);
+            const uint32_t wp0 = funnel(wpg[1], wpg[0], (int)sp);
+            const uint32_t wp1 = funnel(wpg[2], wpg[1], (int)sp);
+            const uint32_t wq0 = funnel(wqg[1], wqg[0], (int)(1u - sp));
+            const uint32_t wq1 = funnel(wqg[2], wqg[1], (int)(1u - sp));
+            uint32_t r = popc((wp0 ^ wq0) & m0) + popc((wp1 ^ wq1) & m1);
+            if (g >= 2) {
+                const uint32_t wp2 = funnel(wpg[3], wpg[2], (int)sp);
+                const uint32_t wq2 = funnel(wqg[3], wqg[2], (int)(1u - sp));
+                r += popc((wp2 ^ wq2) & m2);
+            }
+            rc[g] = (int32_t)r;
+        }
     }
 
     // C' to LDS (for the excluded-shift term), whether C' fits int8, and C' bytes for the B
@@ -387,34 +452,16 @@ struct MfmaWalker {
     __device__ __forceinline__ void score(int32_t (&isl_j)[G])
     {
         const int lane = this->lane;
-        // the part without T first (bit-string and table reads that do not wait for the tile):
+        // the part without T first (table reads that do not wait for the tile):
         // base_j = ISL + 16 hc - 64 rc' + 8 (-1)^(c-j) C'_{kappa_d}
         int32_t base[G];
-        {
-            const uint32_t sp = (uint32_t)(lane + 1); // window shifts: h+1 and kNA-h = 1 - sp (mod 32)
-            const lds_cu32 *wp = (const lds_cu32 *)(uintptr_t)wpa;
-            const lds_cu32 *wq = (const lds_cu32 *)(uintptr_t)wqa;
 #pragma unroll
-            for (int g = 0; g < G; g++) {
-                const MfmaFlip &f = fc[g];
-                // the second tile's windows start 64 bits further in par, 64 bits earlier in rev
-                const lds_cu32 *wpg = wp + (g & 1) * kParWords + (g < 2 ? 0 : 2);
-                const lds_cu32 *wqg = wq + (g & 1) * kRevWords - (g < 2 ? 0 : 2);
-                const uint32_t wp0 = funnel(wpg[1], wpg[0], (int)sp);
-                const uint32_t wp1 = funnel(wpg[2], wpg[1], (int)sp);
-                const uint32_t wq0 = funnel(wqg[1], wqg[0], (int)(1u - sp));
-                const uint32_t wq1 = funnel(wqg[2], wqg[1], (int)(1u - sp));
-                uint32_t rc = bcnt_acc((wp0 ^ wq0) & f.m0, 0u);
-                rc = bcnt_acc((wp1 ^ wq1) & f.m1, rc);
-                if (g >= 2) {
-                    const uint32_t wp2 = funnel(wpg[3], wpg[2], (int)sp);
-                    const uint32_t wq2 = funnel(wqg[3], wqg[2], (int)(1u - sp));
-                    rc = bcnt_acc((wp2 ^ wq2) & f.m2, rc);
-                }
-                // |C'| <= 381: a 24-bit product
-                base[g] = mad24((int32_t)rc, -64, isl + 16 * f.hc) + __mul24(eps8[g & 1], *f.c_kd);
-            }
+        for (int g = 0; g < G; g++) {
+            const MfmaFlip &f = fc[g];
+            // |C'| <= 381: a 24-bit product
+            base[g] = mad24(rc[g], f.rcf, isl + 16 * f.hc) + __mul24(eps8[g & 1], *f.c_kd);
         }
+        (void)lane;
         const mfma_v4i d = tile_all(ta);
         // Z for h = lane sits in lane 63 - lane; |T| <= 191 * 381: 24-bit products
         isl_j[0] = mad24(mult[0], d[0] + __builtin_amdgcn_ds_bpermute(bsrc, d[2]), base[0]);
@@ -459,22 +506,52 @@ struct MfmaWalker {
             const int32_t pv = (lane + 64 * q == kds) ? 0 : (int32_t)pb[64 * q];
             Cv[q] = mad24_u(pv + (int32_t)qb[64 * q], f, Cv[q]);
         }
-        lds_fence();
-        // the flipped symbol and its mirror (m = 2c - js, half index nps) in the bit strings and
-        // in the +-1 byte strings (kind p at byte a, kind 2+p at byte 63 - a when a <= 63, kind 4+p
-        // at byte 127 - a; 0x01 and 0xFF swap under xor 0xFE)
-        // (lane 0: js, lane 1: the mirror; toggles that do not apply xor 0, so there is one branch)
-        if (lane < (js != c ? 2 : 1)) {
-            const int a = lane ? nps : hjs;
-            atomicXor(&lds->par[pis][a >> 5], 1u << (a & 31));
-            const int ar = kNA - 1 - a;
-            atomicXor(&lds->rev[pis][ar >> 5], 1u << (ar & 31));
-            atomicXor(lds->str(pis) + (a >> 2), 0xFEu << (8 * (a & 3)));
-            const int u = 63 - a;
-            atomicXor(lds->str(2 + pis) + (max(u, 0) >> 2), u >= 0 ? 0xFEu << (8 * (u & 3)) : 0u);
+        // rc'_j of the owned flips of js's parity (see the file header).  Partner 2 j - js is s^p at
+        // half index u1 = 2h - hjs >= -63 (-95 big), read from the kind-p string, whose zero pad
+        // covers the negative ones; partner 2 j - m' is s^p at u2 = 2h + hjs + p - c, read as byte
+        // 63 - u2 of the kind-2+p string (127 - u2 of the kind-4+p string when BIG), which holds 0
+        // past the sequence's start; u2 < 64 (< 128) for every flip j < c.  Flips j >= c read
+        // anything and keep it (their rc' is not used).  The term of partner 2 j - js is dropped
+        // where it is the excluded shift of j (js = 3 j - 2c, i.e. 3 h = hjs + c - p), and flip js
+        // itself does not change.
+        const int32_t sjs = bjs ? -1 : 1;                              // s_js before the commit
+        const int32_t emir = (js == c || ((c - js) & 1) == 0) ? 1 : -1; // s_m' = emir s_js
+        {
+            const int32_t eps = (js == c) ? 0 : emir;
+            const int32_t f0 = pis ? 0 : sjs, f1 = pis ? sjs : 0;
+            const int tri = hjs + c - pis;
+            typedef __attribute__((address_space(3))) const int8_t lds_ci8;
+            const uint32_t a1 = (uint32_t)(uintptr_t)lds->str(pis) - (uint32_t)hjs;
+            const uint32_t a2 = (uint32_t)(uintptr_t)lds->str((BIG ? 4 : 2) + pis) + (uint32_t)((BIG ? 127 : 63) - hjs - pis + c);
+#pragma unroll
+            for (int t = 0; t < (BIG ? 2 : 1); t++) {
+                const int32_t h = 64 * t + lane;
+                const int32_t v1 = *(lds_ci8 *)(uintptr_t)(a1 + 2u * (uint32_t)h);
+                const int32_t v2 = *(lds_ci8 *)(uintptr_t)(a2 - 2u * (uint32_t)h);
+                const int32_t t1 = (3 * h == tri) ? 0 : v1;
+                const int32_t d = drop_lane<!BIG>(hjs - 64 * t, mad24_u(v2, eps, t1));
+                rc[2 * t] = mad24_u(d, f0, rc[2 * t]);
+                rc[2 * t + 1] = mad24_u(d, f1, rc[2 * t + 1]);
+            }
+        }
+        // the flipped symbol (lane 0) and its mirror m' = 2c - js (lane 1; the centre again when js
+        // = c) in the +-1 byte strings: kind p at byte a, kind 2+p at byte 63 - a (when a <= 63; a
+        // dummy word otherwise), kind 4+p at byte 127 - a, each written with its new value; the
+        // parity bit strings are rebuilt at the next (re)start.  No byte read above is written here
+        // (the one at the mirror is the excluded shift, whose value is not used).
+        if (lane < 2) {
+            const int a = lane ? (js == c ? hjs : nps) : hjs;
+            const int32_t v = lane ? -emir * sjs : -sjs;
+            int8_t *sp = reinterpret_cast<int8_t *>(lds->str(pis));
+            int8_t *sq = reinterpret_cast<int8_t *>(lds->str(2 + pis));
+            sp[a] = (int8_t)v;
             if constexpr (BIG) {
-                const int u2 = 127 - a; // a <= 95
-                atomicXor(lds->str(4 + pis) + (u2 >> 2), 0xFEu << (8 * (u2 & 3)));
+                int8_t *sr = reinterpret_cast<int8_t *>(lds->str(4 + pis));
+                sr[127 - a] = (int8_t)v; // a <= 95
+                int8_t *q = a <= 63 ? sq + 63 - a : reinterpret_cast<int8_t *>(&lds->book[7]);
+                *q = (int8_t)v;
+            } else {
+                sq[63 - a] = (int8_t)v; // a <= 63
             }
             // the free bit itself (lane 1 xors 0 into a neighbouring word: a lane-varying address keeps
             // the compiler from turning the toggle into a cross-lane reduction)
