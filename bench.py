@@ -11,9 +11,10 @@ unit, Section 3: one evaluated flip = one function evaluation), the roofline of 
 the oracle timed on the host cores on a bounded sample of the same workload, the plain
 one-walk-per-launch form on a sample, and time-to-target statistics (F >= 8, and the lower,
 labelled F >= 5 that most walks reach within the budget); then (unless --no-extras) the L = 101
-batch at low occupancy, an uneven batch of all 52 lengths, the serving workload, the exhaustive
-skew minimum at L = 61 and 69, the best-first search with a bounded queue (with and without the
-second table), and the walk over general sequences at L = 192.
+batch at low occupancy, an uneven batch of all 52 lengths, the serving workload and the saturated
+server, the exhaustive skew minimum at L = 61 and 69, the best-first search with a bounded queue
+(with and without the second table), the first-improvement search with perturbations, and the
+walk over general sequences at L = 192.
 """
 import argparse
 import hashlib
@@ -193,6 +194,30 @@ def serving(labs, rate=20.0, n_requests=100, seed=SEED):
             "wall_s": wall, "ticks": stats["ticks"], "peak_resident_walks": stats["peak_walks"]}
 
 
+def serving_capacity(labs, n_requests=96, seed=SEED + 1):
+    """The server saturated: every request (one odd L uniform in [201, 303], 256 walks, 10^8 flip
+    evaluations, no target) submitted at once, more than the 8 GiB slot pool holds; the aggregate
+    flip-evaluation rate from the first submission to the last completion."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    lengths = rng.choice(np.arange(201, 304, 2), size=n_requests)
+    srv = labs.Server(device_mem_bytes=8 << 30, table_log2=TABLE_LOG2, steps_per_tick=256)
+    t0 = time.perf_counter()
+    jobs = [srv.submit(int(Lr), 256, seed + i, 10 ** 8) for i, Lr in enumerate(lengths)]
+    flips = 0
+    for j in jobs:
+        done, st = srv.wait(j, timeout_ms=600000)
+        flips += st["flip_evals"]
+        srv.release(j)
+    wall = time.perf_counter() - t0
+    stats = srv.stats()
+    srv.close()
+    return {"requests": n_requests, "walks_per_request": 256, "flip_budget_per_request": 10 ** 8,
+            "wall_s": wall, "aggregate_flip_evals_per_s": flips / wall, "ticks": stats["ticks"],
+            "peak_resident_walks": stats["peak_walks"]}
+
+
 def uneven_batch(labs):
     """Every odd L in [201, 303] x 64 walks x 10^6 steps in one launch of mixed shapes,
     replayed from a captured hipGraph."""
@@ -275,6 +300,29 @@ def best_first(labs, walks=WALKS, steps=1000):
                      / (VALU_PEAK_TOPS * 1e12),
                      "mean_best_F": float(np.mean(L * L / (2.0 * best))), "max_best_F": float(L * L / (2.0 * best.min()))}
     return out
+
+
+def first_improvement(labs, walks=WALKS, steps=4768, P=3):
+    """The first-improvement search with perturbations of 3 symbols (Section 2's description of
+    Dimitrov et al.'s method) at the headline length: the evaluations the sequential method counts
+    (j + 1 per move, n + P per perturbation), the flips the kernel scores (n per step, all of them in
+    parallel), and the merit factors reached within the headline's steps per walk."""
+    import numpy as np
+
+    cfg = [labs.make_cfg(L, SEED, w, steps=steps) for w in range(walks)]
+    labs.fi_walk_batch(cfg[:256], P)  # warm the launch path
+    res, ms = labs.fi_walk_batch(cfg, P)
+    evals = sum(r["flip_evals"] for r in res)
+    scored = sum(r["steps_done"] for r in res) * N
+    best = np.array([r["best_isl"] for r in res], dtype=np.float64)
+    alg = scored * ALG_OPS_PER_FLIP / (ms / 1000.0) / 1e12
+    return {"L": L, "searches": walks, "steps": steps, "perturb_bits": P, "kernel_ms": ms,
+            "flip_evals": evals, "flip_evals_per_s": evals / (ms / 1000.0),
+            "scored_flips_per_s": scored / (ms / 1000.0),
+            "perturbations_per_step": sum(r["traps"] for r in res) / sum(r["steps_done"] for r in res),
+            "roofline": dict(matrix_or_alu_roofline(3, alg), alg_ops_per_flip=ALG_OPS_PER_FLIP,
+                             note="algorithmic operations of the scored flips"),
+            "mean_best_F": float(np.mean(L * L / (2.0 * best))), "max_best_F": float(L * L / (2.0 * best.min()))}
 
 
 def general_walk(labs, Lg=192, walks=WALKS, steps=2000):
@@ -375,8 +423,8 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
-    ap.add_argument("--only", choices=["low_occupancy", "uneven_batch", "serving", "enumeration", "best_first",
-                                       "general_walk"],
+    ap.add_argument("--only", choices=["low_occupancy", "uneven_batch", "serving", "serving_capacity", "enumeration",
+                                       "best_first", "general_walk", "first_improvement"],
                     help="run only this measurement and print its JSON (for profiling)")
     ap.add_argument("--probe-lds", action="store_true",
                     help="only measure the LDS read bandwidth (4-, 8- and 16-byte reads per lane) and exit")
@@ -413,6 +461,7 @@ def main():
     set_thresholds(labs)
     if args.only:
         legs = {"low_occupancy": low_occupancy, "uneven_batch": uneven_batch, "serving": serving,
+                "serving_capacity": serving_capacity, "first_improvement": first_improvement,
                 "enumeration": enumeration, "best_first": best_first, "general_walk": general_walk}
         print(json.dumps({args.only: legs[args.only](labs)}), flush=True)
         return
@@ -494,8 +543,10 @@ def main():
         line["low_occupancy"] = low_occupancy(labs)
         line["uneven_batch"] = uneven_batch(labs)
         line["serving"] = serving(labs)
+        line["serving_capacity"] = serving_capacity(labs)
         line["enumeration"] = enumeration(labs)
         line["best_first"] = best_first(labs)
+        line["first_improvement"] = first_improvement(labs)
         line["general_walk"] = general_walk(labs)
     if not args.no_cpu:
         line["cpu_baseline"], _ = cpu_baseline()

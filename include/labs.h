@@ -372,7 +372,8 @@ int labs_autotune_batch(int32_t n_walks, const labs_walk_cfg *cfg, labs_plan_opt
 /* ---------------------------------------------------------------------------------------------
  * Serving: a request loop that admits search jobs by device memory for their walk state, keeps
  * every admitted walk resident across kernel launches and advances all running jobs together
- * (continuous batching).  A job = n_walks walks of one length; each walk's step budget is
+ * (continuous batching; each tick is enqueued before the previous one is summarised, so the GPU
+ * does not wait for the host).  A job = n_walks walks of one length; each walk's step budget is
  * floor(flip_budget / (n_walks * n)); the job stops at its budget or at the first tick
  * boundary (steps_per_tick, 2 steps_per_tick, ... logical steps) at or after the first step at
  * which some walk reached ISL <= ISL_T, where
@@ -430,10 +431,15 @@ int labs_search_wait(labs_server *srv, uint64_t job_id, int64_t timeout_ms,
                      labs_search_status *st);
 /* Cancels a queued or running job; its slots are freed at the next tick.  Thread-safe. */
 int labs_search_cancel(labs_server *srv, uint64_t job_id);
+/* Drops the record of a finished (done or cancelled) job, so that a long-running server does not
+ * keep every past job; afterwards the id is unknown (LABS_ENOTFOUND).  LABS_EPENDING if the job is
+ * still queued or running.  Thread-safe. */
+int labs_search_release(labs_server *srv, uint64_t job_id);
 /* Server counters: ticks run, walks resident now, peak resident walks, flip evaluations done. */
 int labs_server_stats(labs_server *srv, int64_t *ticks, int32_t *resident_walks,
                       int32_t *peak_walks, int64_t *flip_evals);
-/* Stops the scheduler (running jobs are cancelled) and frees everything. */
+/* Stops the scheduler, ends every job still queued or running as cancelled, and frees everything.
+ * No other call on srv may run concurrently with or after it. */
 void labs_server_destroy(labs_server *srv);
 
 #ifdef __cplusplus

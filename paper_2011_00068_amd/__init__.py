@@ -49,7 +49,7 @@ EXPORTS = [
     "labs_walk_plan_get_opts", "labs_walk_plan_last_timing", "labs_walk_plan_destroy",
     "labs_autotune", "labs_autotune_batch", "labs_pq_walk_batch", "labs_fi_walk_batch", "labs_general_walk_batch", "labs_general_flip_scores_dev",
     "labs_server_create", "labs_search_submit", "labs_search_poll", "labs_search_wait",
-    "labs_search_cancel", "labs_server_stats", "labs_server_destroy",
+    "labs_search_cancel", "labs_search_release", "labs_server_stats", "labs_server_destroy",
 ]
 
 
@@ -217,6 +217,7 @@ def lib():
     L.labs_search_poll.argtypes = [vp, u64, P(SearchStatus)]
     L.labs_search_wait.argtypes = [vp, u64, i64, P(SearchStatus)]
     L.labs_search_cancel.argtypes = [vp, u64]
+    L.labs_search_release.argtypes = [vp, u64]
     L.labs_server_stats.argtypes = [vp, P(i64), P(i32), P(i32), P(i64)]
     L.labs_server_destroy.argtypes = [vp]
     L.labs_server_destroy.restype = None
@@ -615,6 +616,10 @@ class Server:
 
     def cancel(self, job_id):
         _check(lib().labs_search_cancel(self._h, job_id), "labs_search_cancel")
+
+    def release(self, job_id):
+        """Drops a finished job's record (labs_search_release)."""
+        _check(lib().labs_search_release(self._h, job_id), "labs_search_release")
 
     def stats(self):
         ticks, res, peak, flips = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()

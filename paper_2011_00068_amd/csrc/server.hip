@@ -4,10 +4,14 @@
 // (each slot = one resident walk state plus its visited table) and a scheduler thread.  Every
 // tick the scheduler admits queued jobs whose walks fit in the free slots, advances every
 // resident walk by steps_per_tick logical steps in one launch of the walk kernel (mixed lengths
-// in one grid), reads the walk states back into pinned memory, and retires jobs that reached
-// their budget or saw a target hit.  Because all walks of a job start together and advance in
-// lockstep of steps_per_tick logical steps, and a job can only stop at those boundaries, its
-// result is a function of the request alone, whatever else shares the GPU.
+// in one grid), reads the walk states back into one of two pinned snapshots, and retires jobs
+// that reached their budget or saw a target hit.  Ticks overlap: tick k is enqueued before the
+// host summarises the snapshot of tick k-1, so the GPU does not wait for the host.  A job that
+// stopped at tick k-1 may still be advanced by tick k (its walks are already done, or the extra
+// steps are discarded); its result comes from the snapshot of the tick it stopped at.  Because
+// all walks of a job start together and advance in lockstep of steps_per_tick logical steps, and a
+// job can only stop at those boundaries, its result is a function of the request alone, whatever
+// else shares the GPU.
 
 #include <algorithm>
 #include <atomic>
@@ -40,6 +44,7 @@ struct Job {
     int64_t isl_t = -1;  // integer target, -1 = none
     int32_t state = LABS_JOB_QUEUED;
     bool cancel = false;
+    int64_t first_tick = -1; // the first tick that advanced its walks
     std::vector<int32_t> slots;
     labs_search_status st{};
 };
@@ -60,8 +65,10 @@ struct labs_server {
     WalkState *d_states = nullptr;
     uint64_t *d_tables = nullptr;
     int32_t *d_order = nullptr;
-    WalkState *h_states = nullptr; // pinned
-    int32_t *h_order = nullptr;    // pinned
+    WalkState *h_states = nullptr;   // pinned: fresh states uploaded at admission
+    WalkState *h_snap[2] = {};       // pinned: walk states read back after ticks (alternating)
+    int32_t *h_order[2] = {};        // pinned: active slot lists of the ticks (alternating)
+    hipEvent_t ev[2] = {};           // end of each alternating tick's readback
     std::vector<int32_t> free_slots;
 
     std::mutex mu;
@@ -92,14 +99,14 @@ void finish_job(labs_server *S, Job &j, int32_t state)
     j.slots.clear();
 }
 
-// Summarise a job from its walks' resident states (after a tick).
-void summarise(labs_server *S, Job &j)
+// Summarise a job from its walks' states in a tick's snapshot.
+void summarise(const WalkState *snap, Job &j)
 {
     int64_t best = INT64_MAX, hit = -1, steps_done = INT64_MAX, fl = 0;
     int32_t best_w = -1, hit_w = -1;
     const WalkState *best_ws = nullptr;
     for (int32_t w = 0; w < (int32_t)j.slots.size(); w++) {
-        const WalkState &ws = S->h_states[j.slots[(size_t)w]];
+        const WalkState &ws = snap[j.slots[(size_t)w]];
         if (ws.best_isl < best) {
             best = ws.best_isl;
             best_w = w;
@@ -123,6 +130,15 @@ void summarise(labs_server *S, Job &j)
         memcpy(j.st.best_bits, best_ws->best_x, sizeof j.st.best_bits);
 }
 
+void cancel_all(labs_server *S)
+{
+    for (auto &kv : S->jobs)
+        if (kv.second.state == LABS_JOB_RUNNING || kv.second.state == LABS_JOB_QUEUED)
+            finish_job(S, kv.second, LABS_JOB_CANCELLED);
+    S->queue.clear();
+    S->cv_done.notify_all();
+}
+
 void scheduler(labs_server *S)
 {
     WalkLaunch lp{};
@@ -135,8 +151,13 @@ void scheduler(labs_server *S)
     lp.chunk = S->opts.steps_per_tick;
     lp.persistent = 0;
     std::vector<int32_t> fresh;
+    int64_t tick = 0;         // ticks enqueued so far
+    bool in_flight = false;   // tick - 1 is enqueued and not summarised yet
+    hipError_t e = hipSuccess;
     while (true) {
         int32_t n_active = 0;
+        const int cur = (int)(tick & 1);
+        bool idle = false;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             // retire cancelled running jobs
@@ -145,9 +166,11 @@ void scheduler(labs_server *S)
                 if (j.state == LABS_JOB_RUNNING && j.cancel)
                     finish_job(S, j, LABS_JOB_CANCELLED);
             }
-            // admit queued jobs in arrival order while their walks fit
+            // admit queued jobs in arrival order while their walks fit (slots freed by the last
+            // summary are free on the GPU once the ticks already enqueued have run: the uploads
+            // below follow them on the stream)
             fresh.clear();
-            while (!S->queue.empty()) {
+            while (!S->stop && !S->queue.empty()) {
                 Job &j = S->jobs[S->queue.front()];
                 if (j.cancel) {
                     S->queue.pop_front();
@@ -159,6 +182,7 @@ void scheduler(labs_server *S)
                 j.state = LABS_JOB_RUNNING;
                 j.st.state = LABS_JOB_RUNNING;
                 j.st.t_admit = now_s(S->t0);
+                j.first_tick = tick;
                 for (int32_t w = 0; w < j.req.n_walks; w++) {
                     const int32_t slot = S->free_slots.back();
                     S->free_slots.pop_back();
@@ -189,72 +213,102 @@ void scheduler(labs_server *S)
                 if (j.state != LABS_JOB_RUNNING)
                     continue;
                 for (int32_t s : j.slots)
-                    S->h_order[n_active++] = s;
+                    S->h_order[cur][n_active++] = s;
             }
             S->resident.store(n_active);
             if (n_active > S->peak.load())
                 S->peak.store(n_active);
-            if (n_active == 0) {
+            if (n_active == 0 && !in_flight) {
                 if (S->stop)
                     break;
                 S->cv_work.wait_for(lk, std::chrono::milliseconds(50));
                 continue;
             }
+            idle = n_active == 0;
         }
-        // one tick on the GPU: upload fresh states and the active list, advance, read back
-        hipError_t e = hipSuccess;
-        for (int32_t slot : fresh) {
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(S->d_states + slot, S->h_states + slot, sizeof(WalkState), hipMemcpyHostToDevice,
-                                   S->stream);
-        }
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(S->d_order, S->h_order, sizeof(int32_t) * (size_t)n_active, hipMemcpyHostToDevice,
-                               S->stream);
-        if (e == hipSuccess)
-            e = launch_walk(lp, S->d_states, n_active, S->d_order, S->d_tables, nullptr, nullptr, nullptr, S->stream);
-        if (e == hipSuccess) {
-            // read back the slots in use (contiguous copy of the span they cover)
-            int32_t lo = INT32_MAX, hi = -1;
-            for (int32_t i = 0; i < n_active; i++) {
-                lo = std::min(lo, S->h_order[i]);
-                hi = std::max(hi, S->h_order[i]);
+        // enqueue tick `tick`: upload fresh states and the active list, advance, read back into
+        // this tick's snapshot (the span of slots in use)
+        if (!idle) {
+            for (int32_t slot : fresh) {
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(S->d_states + slot, S->h_states + slot, sizeof(WalkState),
+                                       hipMemcpyHostToDevice, S->stream);
             }
-            e = hipMemcpyAsync(S->h_states + lo, S->d_states + lo, sizeof(WalkState) * (size_t)(hi - lo + 1),
-                               hipMemcpyDeviceToHost, S->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(S->d_order, S->h_order[cur], sizeof(int32_t) * (size_t)n_active,
+                                   hipMemcpyHostToDevice, S->stream);
+            if (e == hipSuccess)
+                e = launch_walk(lp, S->d_states, n_active, S->d_order, S->d_tables, nullptr, nullptr, nullptr,
+                                S->stream);
+            if (e == hipSuccess) {
+                int32_t lo = INT32_MAX, hi = -1;
+                for (int32_t i = 0; i < n_active; i++) {
+                    lo = std::min(lo, S->h_order[cur][i]);
+                    hi = std::max(hi, S->h_order[cur][i]);
+                }
+                e = hipMemcpyAsync(S->h_snap[cur] + lo, S->d_states + lo, sizeof(WalkState) * (size_t)(hi - lo + 1),
+                                   hipMemcpyDeviceToHost, S->stream);
+            }
+            if (e == hipSuccess)
+                e = hipEventRecord(S->ev[cur], S->stream);
         }
-        if (e == hipSuccess)
-            e = hipStreamSynchronize(S->stream);
-        S->ticks.fetch_add(1);
+        // summarise the previous tick while this one runs
+        if (e == hipSuccess && in_flight)
+            e = hipEventSynchronize(S->ev[cur ^ 1]);
         std::unique_lock<std::mutex> lk(S->mu);
         if (e != hipSuccess) {
             S->device_error = hip_fail(e, "server tick");
-            for (auto &kv : S->jobs)
-                if (kv.second.state == LABS_JOB_RUNNING || kv.second.state == LABS_JOB_QUEUED)
-                    finish_job(S, kv.second, LABS_JOB_CANCELLED);
-            S->queue.clear();
-            S->cv_done.notify_all();
+            cancel_all(S);
             break;
         }
-        int64_t tick_flips = 0;
-        for (auto &kv : S->jobs) {
-            Job &j = kv.second;
-            if (j.state != LABS_JOB_RUNNING)
-                continue;
-            const int64_t before = j.st.flip_evals;
-            summarise(S, j);
-            tick_flips += j.st.flip_evals - before;
-            bool all_done = true;
-            for (int32_t s : j.slots)
-                all_done = all_done && S->h_states[s].status == kDone;
-            if (all_done || j.st.hit_step >= 0 || j.cancel)
-                finish_job(S, j, j.cancel ? LABS_JOB_CANCELLED : LABS_JOB_DONE);
+        if (in_flight) {
+            S->ticks.fetch_add(1);
+            const WalkState *snap = S->h_snap[cur ^ 1];
+            int64_t tick_flips = 0;
+            for (auto &kv : S->jobs) {
+                Job &j = kv.second;
+                // jobs admitted after the summarised tick have no state in its snapshot
+                if (j.state != LABS_JOB_RUNNING || j.first_tick > tick - 1)
+                    continue;
+                const int64_t before = j.st.flip_evals;
+                summarise(snap, j);
+                tick_flips += j.st.flip_evals - before;
+                bool all_done = true;
+                for (int32_t s : j.slots)
+                    all_done = all_done && snap[s].status == kDone;
+                if (all_done || j.st.hit_step >= 0 || j.cancel)
+                    finish_job(S, j, j.cancel ? LABS_JOB_CANCELLED : LABS_JOB_DONE);
+            }
+            S->flips.fetch_add(tick_flips);
+            S->cv_done.notify_all();
         }
-        S->flips.fetch_add(tick_flips);
-        S->cv_done.notify_all();
-        if (S->stop)
+        in_flight = !idle;
+        if (!idle)
+            tick++;
+        if (S->stop && !in_flight)
             break;
     }
+    // a stopped server leaves no tick in flight
+    if (in_flight)
+        (void)hipEventSynchronize(S->ev[(tick - 1) & 1]);
+}
+
+} // namespace
+
+namespace {
+
+void free_server_memory(labs_server *S)
+{
+    if (S->d_states) (void)hipFree(S->d_states);
+    if (S->d_tables) (void)hipFree(S->d_tables);
+    if (S->d_order) (void)hipFree(S->d_order);
+    if (S->h_states) (void)hipHostFree(S->h_states);
+    for (int b = 0; b < 2; b++) {
+        if (S->h_snap[b]) (void)hipHostFree(S->h_snap[b]);
+        if (S->h_order[b]) (void)hipHostFree(S->h_order[b]);
+        if (S->ev[b]) (void)hipEventDestroy(S->ev[b]);
+    }
+    if (S->stream) (void)hipStreamDestroy(S->stream);
 }
 
 } // namespace
@@ -297,18 +351,22 @@ extern "C" int labs_server_create(const labs_server_opts *opts, labs_server **sr
     if (e == hipSuccess) e = hipMalloc(&S->d_tables, sizeof(uint64_t) * (size_t)(slots * S->table_words));
     if (e == hipSuccess) e = hipMalloc(&S->d_order, sizeof(int32_t) * (size_t)slots);
     if (e == hipSuccess) e = hipHostMalloc((void **)&S->h_states, sizeof(WalkState) * (size_t)slots, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&S->h_order, sizeof(int32_t) * (size_t)slots, hipHostMallocDefault);
+    for (int b = 0; b < 2; b++) {
+        if (e == hipSuccess)
+            e = hipHostMalloc((void **)&S->h_snap[b], sizeof(WalkState) * (size_t)slots, hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostMalloc((void **)&S->h_order[b], sizeof(int32_t) * (size_t)slots, hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&S->ev[b], hipEventDisableTiming);
+    }
     if (e != hipSuccess) {
-        if (S->d_states) (void)hipFree(S->d_states);
-        if (S->d_tables) (void)hipFree(S->d_tables);
-        if (S->d_order) (void)hipFree(S->d_order);
-        if (S->h_states) (void)hipHostFree(S->h_states);
-        if (S->h_order) (void)hipHostFree(S->h_order);
-        if (S->stream) (void)hipStreamDestroy(S->stream);
+        free_server_memory(S);
         delete S;
         return hip_fail(e, "labs_server_create");
     }
     memset(S->h_states, 0, sizeof(WalkState) * (size_t)slots);
+    for (int b = 0; b < 2; b++)
+        memset(S->h_snap[b], 0, sizeof(WalkState) * (size_t)slots);
     for (int32_t s = (int32_t)slots - 1; s >= 0; s--)
         S->free_slots.push_back(s);
     S->worker = std::thread(scheduler, S);
@@ -384,8 +442,11 @@ extern "C" int labs_search_wait(labs_server *S, uint64_t job_id, int64_t timeout
         }
         if (timeout_ms >= 0) {
             if (S->cv_done.wait_until(lk, deadline) == std::cv_status::timeout) {
-                *st = S->jobs[job_id].st;
-                const int32_t s2 = S->jobs[job_id].state;
+                auto it2 = S->jobs.find(job_id);
+                if (it2 == S->jobs.end())
+                    return fail(LABS_ENOTFOUND, "unknown job %llu", (unsigned long long)job_id);
+                *st = it2->second.st;
+                const int32_t s2 = it2->second.state;
                 return (s2 == LABS_JOB_DONE || s2 == LABS_JOB_CANCELLED) ? LABS_OK : LABS_EPENDING;
             }
         } else {
@@ -428,6 +489,21 @@ extern "C" int labs_server_stats(labs_server *S, int64_t *ticks, int32_t *reside
     return LABS_OK;
 }
 
+extern "C" int labs_search_release(labs_server *S, uint64_t job_id)
+{
+    if (!S)
+        return fail(LABS_EINVAL, "NULL server");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->jobs.find(job_id);
+    if (it == S->jobs.end())
+        return fail(LABS_ENOTFOUND, "unknown job %llu", (unsigned long long)job_id);
+    const int32_t st = it->second.state;
+    if (st != LABS_JOB_DONE && st != LABS_JOB_CANCELLED)
+        return fail(LABS_EPENDING, "job %llu is not finished", (unsigned long long)job_id);
+    S->jobs.erase(it);
+    return LABS_OK;
+}
+
 extern "C" void labs_server_destroy(labs_server *S)
 {
     if (!S)
@@ -438,17 +514,16 @@ extern "C" void labs_server_destroy(labs_server *S)
         for (auto &kv : S->jobs)
             if (kv.second.state == LABS_JOB_RUNNING || kv.second.state == LABS_JOB_QUEUED)
                 kv.second.cancel = true;
-        S->queue.clear();
         S->cv_work.notify_all();
     }
     if (S->worker.joinable())
         S->worker.join();
+    {
+        // every job still queued or running ends cancelled (and its waiters wake up)
+        std::unique_lock<std::mutex> lk(S->mu);
+        cancel_all(S);
+    }
     (void)hipStreamSynchronize(S->stream);
-    (void)hipFree(S->d_states);
-    (void)hipFree(S->d_tables);
-    (void)hipFree(S->d_order);
-    (void)hipHostFree(S->h_states);
-    (void)hipHostFree(S->h_order);
-    (void)hipStreamDestroy(S->stream);
+    free_server_memory(S);
     delete S;
 }

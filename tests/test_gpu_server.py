@@ -169,3 +169,28 @@ def test_zero_budget_job(labs):
     assert done and st["steps_done"] == 0 and st["flip_evals"] == 0
     starts = [o.isl(o.skew_expand(31, o.start_bits(31, SEED, w, 0))) for w in range(2)]
     assert st["best_isl"] == min(starts)
+
+
+def test_release_finished_jobs(labs):
+    srv = labs.Server(device_mem_bytes=16 * PER_WALK_BYTES, table_log2=TABLE_LOG2, steps_per_tick=64)
+    long_job = srv.submit(255, 4, SEED, 4 * 128 * 10 ** 6)  # runs far longer than the test
+    short = srv.submit(31, 2, SEED, 2 * 16 * 500)
+    done, st = srv.wait(short, timeout_ms=60000)
+    assert done and st["state"] == labs.JOB_DONE
+    with pytest.raises(labs.LabsError) as e:
+        srv.release(long_job)  # still running
+    assert e.value.code == labs.LABS_EPENDING
+    srv.release(short)
+    for call in (srv.poll, srv.release, srv.cancel):
+        with pytest.raises(labs.LabsError) as e:
+            call(short)
+        assert e.value.code == labs.LABS_ENOTFOUND
+    srv.cancel(long_job)
+    done, st = srv.wait(long_job, timeout_ms=60000)
+    assert done and st["state"] == labs.JOB_CANCELLED
+    srv.release(long_job)
+    # a server with many released jobs keeps working: the next job still matches the oracle
+    jid = srv.submit(61, 3, SEED + 9, 3 * 31 * 300)
+    done, st = srv.wait(jid, timeout_ms=60000)
+    srv.close()
+    assert job_view(labs, st, 61) == oracle_job(61, 3, SEED + 9, 300, -1, 64)
