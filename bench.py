@@ -218,6 +218,35 @@ def serving_capacity(labs, n_requests=96, seed=SEED + 1):
             "peak_resident_walks": stats["peak_walks"]}
 
 
+def latency(labs, steps=200000):
+    """Where a walk step's time goes when the GPU is not full (run with --only latency): the uneven
+    batch (52 lengths x 64 walks, one launch) with visited tables of 2^16 and of 2^8 words (the latter
+    always in cache), one walk per length alone (52 waves), and L = 255 batches of 1, 1,024, 3,328
+    and 8,192 walks (1 .. 8 waves per SIMD); microseconds per step of the launch."""
+    import torch
+
+    def timed(cfg):
+        plan = labs.WalkPlan(cfg)
+        plan.run()
+        torch.cuda.synchronize()
+        plan.run()
+        ms, _ = plan.last_timing()
+        plan.close()
+        return ms
+
+    out = {"steps": steps, "uneven_us_per_step": {}, "one_walk_per_length_us_per_step": {}, "l255_us_per_step": {}}
+    lengths = range(201, 304, 2)
+    for tl in (16, 8):
+        cfg = [labs.make_cfg(Lx, SEED, w, steps=steps, table_log2=tl) for Lx in lengths for w in range(64)]
+        out["uneven_us_per_step"][f"table_2^{tl}"] = timed(cfg) * 1000.0 / steps
+        cfg = [labs.make_cfg(Lx, SEED, 0, steps=steps, table_log2=tl) for Lx in lengths]
+        out["one_walk_per_length_us_per_step"][f"table_2^{tl}"] = timed(cfg) * 1000.0 / steps
+    for nw in (1, 1024, 3328, 8192):
+        cfg = [labs.make_cfg(L, SEED, w, steps=steps // 4, table_log2=TABLE_LOG2) for w in range(nw)]
+        out["l255_us_per_step"][f"{nw}_walks"] = timed(cfg) * 1000.0 / (steps // 4)
+    return out
+
+
 def uneven_batch(labs):
     """Every odd L in [201, 303] x 64 walks x 10^6 steps in one launch of mixed shapes,
     replayed from a captured hipGraph."""
@@ -424,7 +453,7 @@ def main():
                     help="only run a plain device-to-device copy of BYTES bytes (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
     ap.add_argument("--only", choices=["low_occupancy", "uneven_batch", "serving", "serving_capacity", "enumeration",
-                                       "best_first", "general_walk", "first_improvement"],
+                                       "best_first", "general_walk", "first_improvement", "latency"],
                     help="run only this measurement and print its JSON (for profiling)")
     ap.add_argument("--probe-lds", action="store_true",
                     help="only measure the LDS read bandwidth (4-, 8- and 16-byte reads per lane) and exit")
@@ -462,6 +491,7 @@ def main():
     if args.only:
         legs = {"low_occupancy": low_occupancy, "uneven_batch": uneven_batch, "serving": serving,
                 "serving_capacity": serving_capacity, "first_improvement": first_improvement,
+                "latency": latency,
                 "enumeration": enumeration, "best_first": best_first, "general_walk": general_walk}
         print(json.dumps({args.only: legs[args.only](labs)}), flush=True)
         return
