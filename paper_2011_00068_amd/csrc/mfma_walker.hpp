@@ -108,14 +108,22 @@ using WaveLdsMfmaBig = WaveLdsMfmaT<6, 92, 74, 192>;
 static_assert(offsetof(WaveLdsMfma, sbuf) % 16 == 0 && offsetof(WaveLdsMfmaBig, sbuf) % 16 == 0,
               "strings 16-byte aligned");
 
-// v in every lane but lane b (a uniform index; no lane when b is outside 0..63, unless IN_RANGE
-// promises 0 <= b < 64), 0 in lane b: one v_cndmask with the lane mask built on the scalar unit
-template <bool IN_RANGE>
-__device__ __forceinline__ int32_t drop_lane(int b, int32_t v)
+// v where cond is false, 0 where it is true: one v_cndmask on the lane mask of cond (a select,
+// never a branch around the computation of v)
+__device__ __forceinline__ int32_t drop_where(bool cond, int32_t v)
 {
-    const uint64_t keep = IN_RANGE ? ~(1ull << b) : ((b >= 0 && b < 64) ? ~(1ull << b) : ~0ull);
+    const uint64_t m = __builtin_amdgcn_ballot_w64(cond);
     int32_t r;
-    asm("v_cndmask_b32_e64 %0, 0, %1, %2" : "=v"(r) : "v"(v), "s"(keep));
+    asm("v_cndmask_b32_e64 %0, %1, 0, %2" : "=v"(r) : "v"(v), "s"(m));
+    return r;
+}
+
+// v where cond is false, -v where it is true
+__device__ __forceinline__ int32_t negate_where(bool cond, int32_t v)
+{
+    const uint64_t m = __builtin_amdgcn_ballot_w64(cond);
+    int32_t r;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(v), "v"(-v), "s"(m));
     return r;
 }
 
@@ -479,33 +487,48 @@ struct MfmaWalker {
     template <bool REG_X = true>
     __device__ __forceinline__ void commit(int js, int32_t isl_new)
     {
+        // The index arithmetic of a commit is wave-uniform and runs on the scalar unit; the vector
+        // instructions are the per-lane reads, selects and updates.
         const int lane = this->lane;
         const int ol = (js & 127) >> 1;              // the lane that scores js
         const int slot = (js >> 7) * 2 + (js & 1);   // and its slot
-        // the sign of s_js from the owner lane's mult
+        // mult of js at its owner lane: -8 s_js, or -4 s_c at the centre
         int32_t mj = __builtin_amdgcn_readlane(mult[0], ol);
 #pragma unroll
         for (int g = 1; g < G; g++)
             mj = slot == g ? __builtin_amdgcn_readlane(mult[g], ol) : mj;
-        const uint32_t bjs = mj > 0 ? 1u : 0u;
+        const int32_t f = mj >> 1;                   // -4 s_js (-2 s_c at the centre)
+        const int32_t sjs = ~((mj >> 31) << 1);      // s_js before the commit: -1 if mj > 0, else 1
         const int hjs = js >> 1;
         const int pis = js & 1;
-        const int nps = (js == c) ? 0 : c - ((js + 1) >> 1);
-        const int kds = (js == c) ? -1 : c - 1 - js;
+        // (at the centre js = c these give kds = -1, no excluded shift, and nps = hjs)
+        const int kds = c - 1 - js;                  // the excluded shift kappa_d of js
+        const int nps = c - ((js + 1) >> 1);         // half index of the mirror m' = 2c - js
+        // byte addresses of the strings of kind p, 2+p and (big) 4+p
+        typedef __attribute__((address_space(3))) const int8_t lds_ci8;
+        typedef __attribute__((address_space(3))) int8_t lds_i8;
+        const uint32_t s0 = (uint32_t)(uintptr_t)lds->str(0);
+        const uint32_t sp_a = s0 + (uint32_t)pis * 4u * (uint32_t)(Lds::str_off(1) - Lds::str_off(0));
+        const uint32_t sq_a = sp_a + 4u * (uint32_t)(Lds::str_off(2) - Lds::str_off(0));
+        const uint32_t sr_a = BIG ? (uint32_t)(uintptr_t)lds->str(4) +
+                                        (uint32_t)pis * 4u * (uint32_t)(Lds::str_off(5) - Lds::str_off(4))
+                                  : 0u;
         // dC'_kappa = -4 s_js (p_kappa + q_kappa), p without the excluded shift kappa_d, read from
         // the +-1 byte strings (0 past either end, so lanes with kappa >= c add nothing): p from
         // s^p at hjs + 1 + kappa, q = s^p_{hjs-1-kappa} from the reversed string (s^p_{63-u}, or
         // s^p_{127-u} when half indices reach past 64); at the centre p = q and u = q, so the
         // factor is halved instead
-        const int32_t f = (js == c) ? (bjs ? 2 : -2) : (bjs ? 4 : -4);
-        const int8_t *pb = reinterpret_cast<const int8_t *>(lds->str(pis)) + hjs + 1 + lane;
-        const int8_t *qb = BIG ? reinterpret_cast<const int8_t *>(lds->str(4 + pis)) + 128 - hjs + lane
-                               : reinterpret_cast<const int8_t *>(lds->str(2 + pis)) + 64 - hjs + lane;
+        const uint32_t pb = sp_a + (uint32_t)(hjs + 1);
+        const uint32_t qb = (BIG ? sr_a + 128u : sq_a + 64u) - (uint32_t)hjs;
+        int32_t pv[QR], qv[QR];
 #pragma unroll
         for (int q = 0; q < QR; q++) {
-            const int32_t pv = (lane + 64 * q == kds) ? 0 : (int32_t)pb[64 * q];
-            Cv[q] = mad24_u(pv + (int32_t)qb[64 * q], f, Cv[q]);
+            pv[q] = *(lds_ci8 *)(uintptr_t)(pb + (uint32_t)(lane + 64 * q));
+            qv[q] = *(lds_ci8 *)(uintptr_t)(qb + (uint32_t)(lane + 64 * q));
         }
+#pragma unroll
+        for (int q = 0; q < QR; q++)
+            Cv[q] = mad24_u(drop_where(lane + 64 * q == kds, pv[q]) + qv[q], f, Cv[q]);
         // rc'_j of the owned flips of js's parity (see the file header).  Partner 2 j - js is s^p at
         // half index u1 = 2h - hjs >= -63 (-95 big), read from the kind-p string, whose zero pad
         // covers the negative ones; partner 2 j - m' is s^p at u2 = 2h + hjs + p - c, read as byte
@@ -513,23 +536,20 @@ struct MfmaWalker {
         // past the sequence's start; u2 < 64 (< 128) for every flip j < c.  Flips j >= c read
         // anything and keep it (their rc' is not used).  The term of partner 2 j - js is dropped
         // where it is the excluded shift of j (js = 3 j - 2c, i.e. 3 h = hjs + c - p), and flip js
-        // itself does not change.
-        const int32_t sjs = bjs ? -1 : 1;                              // s_js before the commit
-        const int32_t emir = (js == c || ((c - js) & 1) == 0) ? 1 : -1; // s_m' = emir s_js
+        // itself does not change.  s_m' = (-1)^(c - js) s_js (also at the centre, where m' = js).
+        const int32_t emir = ((c ^ js) & 1) ? -1 : 1;
         {
-            const int32_t eps = (js == c) ? 0 : emir;
-            const int32_t f0 = pis ? 0 : sjs, f1 = pis ? sjs : 0;
+            const int32_t eps = js == c ? 0 : emir;
+            const int32_t f1 = pis ? sjs : 0, f0 = sjs - f1;
             const int tri = hjs + c - pis;
-            typedef __attribute__((address_space(3))) const int8_t lds_ci8;
-            const uint32_t a1 = (uint32_t)(uintptr_t)lds->str(pis) - (uint32_t)hjs;
-            const uint32_t a2 = (uint32_t)(uintptr_t)lds->str((BIG ? 4 : 2) + pis) + (uint32_t)((BIG ? 127 : 63) - hjs - pis + c);
+            const uint32_t a1 = sp_a - (uint32_t)hjs;
+            const uint32_t a2 = (BIG ? sr_a : sq_a) + (uint32_t)((BIG ? 127 : 63) - hjs - pis + c);
 #pragma unroll
             for (int t = 0; t < (BIG ? 2 : 1); t++) {
                 const int32_t h = 64 * t + lane;
                 const int32_t v1 = *(lds_ci8 *)(uintptr_t)(a1 + 2u * (uint32_t)h);
                 const int32_t v2 = *(lds_ci8 *)(uintptr_t)(a2 - 2u * (uint32_t)h);
-                const int32_t t1 = (3 * h == tri) ? 0 : v1;
-                const int32_t d = drop_lane<!BIG>(hjs - 64 * t, mad24_u(v2, eps, t1));
+                const int32_t d = drop_where(h == hjs, mad24_u(v2, eps, drop_where(3 * h == tri, v1)));
                 rc[2 * t] = mad24_u(d, f0, rc[2 * t]);
                 rc[2 * t + 1] = mad24_u(d, f1, rc[2 * t + 1]);
             }
@@ -540,28 +560,25 @@ struct MfmaWalker {
         // parity bit strings are rebuilt at the next (re)start.  No byte read above is written here
         // (the one at the mirror is the excluded shift, whose value is not used).
         if (lane < 2) {
-            const int a = lane ? (js == c ? hjs : nps) : hjs;
+            const int a = lane ? nps : hjs;
             const int32_t v = lane ? -emir * sjs : -sjs;
-            int8_t *sp = reinterpret_cast<int8_t *>(lds->str(pis));
-            int8_t *sq = reinterpret_cast<int8_t *>(lds->str(2 + pis));
-            sp[a] = (int8_t)v;
+            *(lds_i8 *)(uintptr_t)(sp_a + (uint32_t)a) = (int8_t)v;
             if constexpr (BIG) {
-                int8_t *sr = reinterpret_cast<int8_t *>(lds->str(4 + pis));
-                sr[127 - a] = (int8_t)v; // a <= 95
-                int8_t *q = a <= 63 ? sq + 63 - a : reinterpret_cast<int8_t *>(&lds->book[7]);
-                *q = (int8_t)v;
+                *(lds_i8 *)(uintptr_t)(sr_a + 127u - (uint32_t)a) = (int8_t)v; // a <= 95
+                const uint32_t qa = a <= 63 ? sq_a + 63u - (uint32_t)a
+                                            : (uint32_t)(uintptr_t)reinterpret_cast<int8_t *>(&lds->book[7]);
+                *(lds_i8 *)(uintptr_t)qa = (int8_t)v;
             } else {
-                sq[63 - a] = (int8_t)v; // a <= 63
+                *(lds_i8 *)(uintptr_t)(sq_a + 63u - (uint32_t)a) = (int8_t)v; // a <= 63
             }
             // the free bit itself (lane 1 xors 0 into a neighbouring word: a lane-varying address keeps
             // the compiler from turning the toggle into a cross-lane reduction)
             atomicXor(&lds->xw[(js >> 5) ^ lane], lane == 0 ? 1u << (js & 31) : 0u);
         }
         lds_fence();
-        const bool own = lane == ol;
 #pragma unroll
         for (int g = 0; g < G; g++)
-            mult[g] = (own && slot == g) ? -mult[g] : mult[g];
+            mult[g] = negate_where(flip(g) == js, mult[g]);
         if (REG_X)
             xflip_uniform(x, js);
         x0 ^= js < 32 ? 1u << js : 0u;

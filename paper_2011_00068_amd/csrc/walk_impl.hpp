@@ -725,7 +725,9 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
             if (w.isl <= thr)
                 note_state(ts);
         }
-        while (ts < lim) {
+        // One exit, at the bottom: with a second exit (a break) the compiler copies every
+        // loop-carried register once per step on the way back to the top.
+        if (ts < lim) do {
             // Keep per-lane index arithmetic inside the loop instead of pinning ~100 VGPRs of
             // loop invariants for the whole walk: the values are cheap to recompute and the
             // registers are worth more as occupancy.
@@ -797,31 +799,28 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
 
             ts++;
             rem--;
-            if (js < 0) {
-                // trapped: every flip leads to a visited state; restart (the step counts, and
-                // replaces a periodic restart due at the same step)
-                traps++;
-                if (rem == 0)
-                    rem = R32;
-                trap_trp = trp;
-                if (TRACE && trp)
-                    trp += 2;
-                if (TRACE && scp)
-                    scp += n;
-                need_restart = true;
-                break;
-            }
+            // Trapped (every flip leads to a visited state): the walk restarts, which rebuilds all
+            // of the walker's state and clears its table, so committing any flip first (flip 0)
+            // is harmless; the step then takes one path whether or not it trapped.  The trap's
+            // table store is overwritten by the clear (the same lanes store there first).
+            const bool trapped = js < 0;
+            js = trapped ? 0 : js;
             w.template commit<false>(js, isl_new);
             w.h = h_new;
             {
                 const uint32_t s_new = (uint32_t)slot_of(w.h, w.x0, exact, tlog2);
-                if (w.lane == 0)
-                    T[s_new] = w.h | 1ull;
+                // every lane stores the same word to the same address (one memory request, and
+                // no exec mask to save and restore around a one-lane store)
+                uint32_t sv = s_new;
+                asm volatile("" : "+v"(sv));
+                T[sv] = w.h | 1ull;
                 jskip = s_new != slot_cur ? js : -1;
                 slot_cur = s_new;
             }
             if (TRACE && trp) {
-                if (w.lane == 0) {
+                if (trapped)
+                    trap_trp = trp; // written once the restart is done
+                else if (w.lane == 0) {
                     trp[0] = js;
                     trp[1] = w.isl;
                 }
@@ -829,17 +828,14 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
             }
             if (TRACE && scp)
                 scp += n;
-            if (w.isl <= thr)
+            traps += trapped ? 1 : 0;
+            if (!trapped && w.isl <= thr)
                 note_state(ts);
-            if (rem == 0) {
-                rem = R32;
-                // periodic restart (not after the last step, not once stopped)
-                if (ts < left32 && lim >= 0) {
-                    need_restart = true;
-                    break;
-                }
-            }
-        }
+            // a restart after a trap, or the periodic one (not after the last step, not once
+            // stopped); a trap replaces a periodic restart due at the same step
+            need_restart = trapped || (rem == 0 && ts < left32 && lim >= 0);
+            rem = rem == 0 ? R32 : rem;
+        } while (!need_restart && ts < lim);
         if (!need_restart)
             break;
     }
