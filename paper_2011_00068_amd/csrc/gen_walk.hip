@@ -82,6 +82,7 @@ struct GenMfmaWalker {
     int32_t bsrc;         // ds_bpermute source of Z: lane 63 - lane
 
     __device__ __forceinline__ uint32_t *x_lds() const { return lds->xw; }
+    __device__ __forceinline__ void sync_x_lds() {} // every commit keeps lds->xw current
     __device__ __forceinline__ uint32_t *best_lds() const { return lds->bestx; }
     __device__ __forceinline__ int32_t *book_lds() const { return lds->book; }
 

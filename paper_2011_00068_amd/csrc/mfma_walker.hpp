@@ -228,6 +228,28 @@ struct MfmaWalker {
         }
     }
 
+    // The free bits into lds->xw from the kind-p strings (bit j set where s_j = -1): commit<false>
+    // keeps only the strings current, and the walk reads the free bits rarely (a new best state,
+    // the end of a launch).
+    __device__ __forceinline__ void sync_x_lds()
+    {
+        const int lane = this->lane;
+        typedef __attribute__((address_space(3))) const int8_t lds_ci8;
+        const uint32_t s0 = (uint32_t)(uintptr_t)lds->str(0);
+        const uint32_t d1 = 4u * (uint32_t)(Lds::str_off(1) - Lds::str_off(0));
+#pragma unroll
+        for (int r = 0; r < kXWords / 2; r++) {
+            const int j = 64 * r + lane; // half index j / 2 < 96: inside the strings
+            const int32_t v = *(lds_ci8 *)(uintptr_t)(s0 + (uint32_t)(j & 1) * d1 + (uint32_t)(j >> 1));
+            const uint64_t m = ballot(j < n && v < 0);
+            if (lane == 0) {
+                lds->xw[2 * r] = (uint32_t)m;
+                lds->xw[2 * r + 1] = (uint32_t)(m >> 32);
+            }
+        }
+        lds_fence();
+    }
+
     __device__ inline uint32_t seq_bit(int i) const
     {
         if (i < 0 || i >= L)
@@ -571,9 +593,7 @@ struct MfmaWalker {
             } else {
                 *(lds_i8 *)(uintptr_t)(sq_a + 63u - (uint32_t)a) = (int8_t)v; // a <= 63
             }
-            // the free bit itself (lane 1 xors 0 into a neighbouring word: a lane-varying address keeps
-            // the compiler from turning the toggle into a cross-lane reduction)
-            atomicXor(&lds->xw[(js >> 5) ^ lane], lane == 0 ? 1u << (js & 31) : 0u);
+            // (the free bits in lds->xw are not kept: sync_x_lds() reads them off the strings)
         }
         lds_fence();
 #pragma unroll

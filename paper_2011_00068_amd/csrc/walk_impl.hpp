@@ -154,6 +154,7 @@ struct Walker {
     __device__ __forceinline__ uint32_t *x_lds() const { return lds->xw; }
     __device__ __forceinline__ uint32_t *best_lds() const { return lds->bestx; }
     __device__ __forceinline__ int32_t *book_lds() const { return lds->book; }
+    __device__ __forceinline__ void sync_x_lds() {} // every commit keeps lds->xw current
 
     // b_js (uniform) from the lane that scores flip js: mult > 0 iff s_js = -1
     __device__ __forceinline__ uint32_t sbit_of(int js) const
@@ -675,8 +676,11 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
         wf |= nw ? 1 : 0;
         lim = nh ? -1 : lim;
         thr = su(threshold(best, hf != 0, wf != 0));
-        if (nb && w.lane < kXWords)
-            bl[w.lane] = xl[w.lane];
+        if (nb) {
+            w.sync_x_lds();
+            if (w.lane < kXWords)
+                bl[w.lane] = xl[w.lane];
+        }
         if (w.lane == 0) {
             bk[0] = best;
             if (nb)
@@ -757,7 +761,7 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
                     for (int g = 1; g < G; g++)
                         km = min(km, keys[g]);
                     cand[i] = wave_min_u32(km);
-                    if (cand[i] != 0xFFFFFFFFu) {
+                    if (i + 1 < PW && cand[i] != 0xFFFFFFFFu) {
 #pragma unroll
                         for (int g = 0; g < G; g++)
                             keys[g] = (w.flip(g) == (int)(cand[i] & 255u)) ? 0xFFFFFFFFu : keys[g];
@@ -795,6 +799,10 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
                 }
                 if (cand[PW - 1] == 0xFFFFFFFFu)
                     break;
+                // every candidate was visited: drop the last one too before the next round
+#pragma unroll
+                for (int g = 0; g < G; g++)
+                    keys[g] = (w.flip(g) == (int)(cand[PW - 1] & 255u)) ? 0xFFFFFFFFu : keys[g];
             }
 
             ts++;
@@ -811,9 +819,7 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
                 const uint32_t s_new = (uint32_t)slot_of(w.h, w.x0, exact, tlog2);
                 // every lane stores the same word to the same address (one memory request, and
                 // no exec mask to save and restore around a one-lane store)
-                uint32_t sv = s_new;
-                asm volatile("" : "+v"(sv));
-                T[sv] = w.h | 1ull;
+                T[s_new] = w.h | 1ull;
                 jskip = s_new != slot_cur ? js : -1;
                 slot_cur = s_new;
             }
@@ -851,6 +857,7 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
     if (watch_ts >= 0)
         wstep = t0 + watch_ts;
 
+    w.sync_x_lds();
     lds_fence();
     if (lane < kXWords) {
         ws.x[lane] = xl[lane];
