@@ -540,13 +540,15 @@ struct MfmaWalker {
         // s^p at hjs + 1 + kappa, q = s^p_{hjs-1-kappa} from the reversed string (s^p_{63-u}, or
         // s^p_{127-u} when half indices reach past 64); at the centre p = q and u = q, so the
         // factor is halved instead
-        const uint32_t pb = sp_a + (uint32_t)(hjs + 1);
-        const uint32_t qb = (BIG ? sr_a + 128u : sq_a + 64u) - (uint32_t)hjs;
+        // (the uniform bases go through readfirstlane, a no-op on a scalar, so that the per-lane
+        // offsets stay one add and the constant ones fold into the reads' offset fields)
+        lds_ci8 *const pl = (lds_ci8 *)(uintptr_t)su(sp_a + (uint32_t)(hjs + 1)) + lane;
+        lds_ci8 *const ql = (lds_ci8 *)(uintptr_t)su((BIG ? sr_a + 128u : sq_a + 64u) - (uint32_t)hjs) + lane;
         int32_t pv[QR], qv[QR];
 #pragma unroll
         for (int q = 0; q < QR; q++) {
-            pv[q] = *(lds_ci8 *)(uintptr_t)(pb + (uint32_t)(lane + 64 * q));
-            qv[q] = *(lds_ci8 *)(uintptr_t)(qb + (uint32_t)(lane + 64 * q));
+            pv[q] = pl[64 * q];
+            qv[q] = ql[64 * q];
         }
 #pragma unroll
         for (int q = 0; q < QR; q++)
@@ -564,13 +566,14 @@ struct MfmaWalker {
             const int32_t eps = js == c ? 0 : emir;
             const int32_t f1 = pis ? sjs : 0, f0 = sjs - f1;
             const int tri = hjs + c - pis;
-            const uint32_t a1 = sp_a - (uint32_t)hjs;
-            const uint32_t a2 = (BIG ? sr_a : sq_a) + (uint32_t)((BIG ? 127 : 63) - hjs - pis + c);
+            lds_ci8 *const a1 = (lds_ci8 *)(uintptr_t)su(sp_a - (uint32_t)hjs) + 2 * lane;
+            lds_ci8 *const a2 =
+                (lds_ci8 *)(uintptr_t)su((BIG ? sr_a : sq_a) + (uint32_t)((BIG ? 127 : 63) - hjs - pis + c)) - 2 * lane;
 #pragma unroll
             for (int t = 0; t < (BIG ? 2 : 1); t++) {
                 const int32_t h = 64 * t + lane;
-                const int32_t v1 = *(lds_ci8 *)(uintptr_t)(a1 + 2u * (uint32_t)h);
-                const int32_t v2 = *(lds_ci8 *)(uintptr_t)(a2 - 2u * (uint32_t)h);
+                const int32_t v1 = a1[128 * t];
+                const int32_t v2 = a2[-128 * t];
                 const int32_t d = drop_where(h == hjs, mad24_u(v2, eps, drop_where(3 * h == tri, v1)));
                 rc[2 * t] = mad24_u(d, f0, rc[2 * t]);
                 rc[2 * t + 1] = mad24_u(d, f1, rc[2 * t + 1]);

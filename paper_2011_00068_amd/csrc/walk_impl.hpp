@@ -752,20 +752,24 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
             int js = -1;
             int32_t isl_new = 0;
             uint64_t h_new = 0; // hash of the chosen neighbour (from its probe)
+            static_assert(PW >= 1 && PW <= 2, "one or two candidates per probe round");
             while (true) {
+                // candidate i: the smallest key above candidate i - 1, i.e. the smallest of the
+                // keys minus (candidate i - 1) + 1 in unsigned arithmetic, which sends the keys
+                // at or below candidate i - 1 past every other one (keys are distinct but for the
+                // empty key ~0, and a wave holds more keys than candidates)
                 uint32_t cand[PW];
+                uint32_t base = 0;
 #pragma unroll
                 for (int i = 0; i < PW; i++) {
-                    uint32_t km = keys[0];
+                    uint32_t km = keys[0] - base;
 #pragma unroll
                     for (int g = 1; g < G; g++)
-                        km = min(km, keys[g]);
-                    cand[i] = wave_min_u32(km);
-                    if (i + 1 < PW && cand[i] != 0xFFFFFFFFu) {
-#pragma unroll
-                        for (int g = 0; g < G; g++)
-                            keys[g] = (w.flip(g) == (int)(cand[i] & 255u)) ? 0xFFFFFFFFu : keys[g];
-                    }
+                        km = min(km, keys[g] - base);
+                    cand[i] = wave_min_u32(km) + base;
+                    // (on the scalar unit: left to itself the compiler adds on the vector unit to
+                    // reuse the carry as the test for an empty candidate)
+                    asm("s_add_u32 %0, %1, 1" : "=s"(base) : "s"(cand[i]) : "scc");
                 }
                 if (cand[0] == 0xFFFFFFFFu)
                     break; // every flip leads to a visited state
@@ -799,10 +803,13 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
                 }
                 if (cand[PW - 1] == 0xFFFFFFFFu)
                     break;
-                // every candidate was visited: drop the last one too before the next round
+                // every candidate was visited: drop them before the next round
 #pragma unroll
-                for (int g = 0; g < G; g++)
-                    keys[g] = (w.flip(g) == (int)(cand[PW - 1] & 255u)) ? 0xFFFFFFFFu : keys[g];
+                for (int i = 0; i < PW; i++) {
+#pragma unroll
+                    for (int g = 0; g < G; g++)
+                        keys[g] = keys[g] == cand[i] ? 0xFFFFFFFFu : keys[g];
+                }
             }
 
             ts++;
