@@ -512,8 +512,9 @@ struct MfmaWalker {
         // The index arithmetic of a commit is wave-uniform and runs on the scalar unit; the vector
         // instructions are the per-lane reads, selects and updates.
         const int lane = this->lane;
-        const int ol = (js & 127) >> 1;              // the lane that scores js
-        const int slot = (js >> 7) * 2 + (js & 1);   // and its slot
+        // the lane that scores js and its slot (one tile: js < 128, slot = js & 1)
+        const int ol = BIG ? (js & 127) >> 1 : js >> 1;
+        const int slot = BIG ? (js >> 7) * 2 + (js & 1) : js & 1;
         // mult of js at its owner lane: -8 s_js, or -4 s_c at the centre
         int32_t mj = __builtin_amdgcn_readlane(mult[0], ol);
 #pragma unroll
@@ -561,7 +562,7 @@ struct MfmaWalker {
         // anything and keep it (their rc' is not used).  The term of partner 2 j - js is dropped
         // where it is the excluded shift of j (js = 3 j - 2c, i.e. 3 h = hjs + c - p), and flip js
         // itself does not change.  s_m' = (-1)^(c - js) s_js (also at the centre, where m' = js).
-        const int32_t emir = ((c ^ js) & 1) ? -1 : 1;
+        const int32_t emir = 1 - 2 * ((c ^ js) & 1);
         {
             const int32_t eps = js == c ? 0 : emir;
             const int32_t f1 = pis ? sjs : 0, f0 = sjs - f1;

@@ -753,12 +753,14 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
             int32_t isl_new = 0;
             uint64_t h_new = 0; // hash of the chosen neighbour (from its probe)
             static_assert(PW >= 1 && PW <= 2, "one or two candidates per probe round");
-            while (true) {
+            uint32_t cand[PW];
+            // One round: the PW best keys, probed together; true when it settles the step (a move
+            // found, or no candidate left).
+            auto probe_round = [&]() -> bool {
                 // candidate i: the smallest key above candidate i - 1, i.e. the smallest of the
                 // keys minus (candidate i - 1) + 1 in unsigned arithmetic, which sends the keys
                 // at or below candidate i - 1 past every other one (keys are distinct but for the
                 // empty key ~0, and a wave holds more keys than candidates)
-                uint32_t cand[PW];
                 uint32_t base = 0;
 #pragma unroll
                 for (int i = 0; i < PW; i++) {
@@ -772,7 +774,7 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
                     asm("s_add_u32 %0, %1, 1" : "=s"(base) : "s"(cand[i]) : "scc");
                 }
                 if (cand[0] == 0xFFFFFFFFu)
-                    break; // every flip leads to a visited state
+                    return true; // every flip leads to a visited state
                 // lane i probes candidate i
                 uint32_t my = cand[0];
 #pragma unroll
@@ -799,17 +801,21 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
                     isl_new = (int32_t)(pick >> 8);
                     h_new = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(hc >> 32), first) << 32) |
                             (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)hc, first);
-                    break;
+                    return true;
                 }
-                if (cand[PW - 1] == 0xFFFFFFFFu)
-                    break;
-                // every candidate was visited: drop them before the next round
+                return cand[PW - 1] == 0xFFFFFFFFu; // no candidate left for another round
+            };
+            // the first round settles almost every step; the loop after it is the rare case of PW
+            // visited candidates in a row
+            if (!probe_round()) {
+                do {
 #pragma unroll
-                for (int i = 0; i < PW; i++) {
+                    for (int i = 0; i < PW; i++) {
 #pragma unroll
-                    for (int g = 0; g < G; g++)
-                        keys[g] = keys[g] == cand[i] ? 0xFFFFFFFFu : keys[g];
-                }
+                        for (int g = 0; g < G; g++)
+                            keys[g] = keys[g] == cand[i] ? 0xFFFFFFFFu : keys[g];
+                    }
+                } while (!probe_round());
             }
 
             ts++;
@@ -825,8 +831,11 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
             {
                 const uint32_t s_new = (uint32_t)slot_of(w.h, w.x0, exact, tlog2);
                 // every lane stores the same word to the same address (one memory request, and
-                // no exec mask to save and restore around a one-lane store)
-                T[s_new] = w.h | 1ull;
+                // no exec mask to save and restore around a one-lane store); the address is
+                // formed on the vector unit (one 64-bit shift-add instead of four scalar ops)
+                uint32_t sv = s_new;
+                asm volatile("" : "+v"(sv));
+                T[sv] = w.h | 1ull;
                 jskip = s_new != slot_cur ? js : -1;
                 slot_cur = s_new;
             }
