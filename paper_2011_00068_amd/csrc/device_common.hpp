@@ -160,6 +160,16 @@ __device__ inline uint32_t bcnt_acc(uint32_t x, uint32_t acc)
     return r;
 }
 
+// v with lane L replaced by the wave-uniform x (one v_writelane_b32; readfirstlane, free on a value
+// already in a scalar register, makes x a scalar operand, and the lane is an inline constant)
+template <int L>
+__device__ inline int32_t write_lane(int32_t v, int32_t x)
+{
+    static_assert(L >= 0 && L < 64, "a lane of the wave");
+    asm("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(__builtin_amdgcn_readfirstlane(x)), "n"(L));
+    return v;
+}
+
 // a * b + acc for a, b in the signed 24-bit range, as one full-rate v_mad_i32_i24 (the generic
 // 32-bit multiply is a multi-pass instruction).
 __device__ inline int32_t mad24(int32_t a, int32_t b, int32_t acc)

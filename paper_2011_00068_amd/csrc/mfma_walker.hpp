@@ -586,8 +586,9 @@ struct MfmaWalker {
         // parity bit strings are rebuilt at the next (re)start.  No byte read above is written here
         // (the one at the mirror is the excluded shift, whose value is not used).
         if (lane < 2) {
-            const int a = lane ? nps : hjs;
-            const int32_t v = lane ? -emir * sjs : -sjs;
+            // (per-lane values by v_writelane: lane 0's replaces lane 1's, no compare and select)
+            const int a = write_lane<0>(nps, hjs);
+            const int32_t v = write_lane<0>(-emir * sjs, -sjs);
             *(lds_i8 *)(uintptr_t)(sp_a + (uint32_t)a) = (int8_t)v;
             if constexpr (BIG) {
                 *(lds_i8 *)(uintptr_t)(sr_a + 127u - (uint32_t)a) = (int8_t)v; // a <= 95

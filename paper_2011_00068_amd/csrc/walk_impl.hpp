@@ -777,9 +777,8 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
                     return true; // every flip leads to a visited state
                 // lane i probes candidate i
                 uint32_t my = cand[0];
-#pragma unroll
-                for (int i = 1; i < PW; i++)
-                    my = (w.lane == i) ? cand[i] : my;
+                if constexpr (PW > 1)
+                    my = (uint32_t)write_lane<1>((int32_t)my, (int32_t)cand[1]);
                 const int jm = min((int)(my & 255u), n - 1);
                 const uint64_t hc = w.h ^ zk[jm];
                 const uint32_t x0 = w.x0 ^ (jm < 32 ? 1u << (jm & 31) : 0u);
