@@ -215,7 +215,7 @@ typedef struct labs_walk_result {
 
 /* Kernel variants: results never depend on the choice. */
 #define LABS_VARIANT_AUTO 0     /* autotuned (labs_autotune cache), else LABS_VARIANT_MFMA when
-                                   every walk has L >= 129, else LABS_VARIANT_BITSLICE */
+                                   every walk has L <= 383, else LABS_VARIANT_BITSLICE */
 #define LABS_VARIANT_BITSLICE 1 /* bit-sliced correlation table, popcount scoring */
 #define LABS_VARIANT_DIRECT 2   /* int8 sequence + int32 table in LDS, direct sum of squares */
 #define LABS_VARIANT_MFMA 3     /* the correlation sums of every flip as int8 matrix-core tiles:

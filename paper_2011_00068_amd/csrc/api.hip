@@ -986,8 +986,8 @@ static int resolve_opts(labs_walk_plan *p, const labs_plan_opts *in)
     }
     labs_plan_opts tuned{};
     const bool have = cache_lookup(minL, maxL, &tuned);
-    // untuned default: the matrix-core scoring where it was measured faster (L >= 129),
-    // the bit-sliced one elsewhere
+    // untuned default: the matrix-core scoring (measured faster than the bit-sliced one at every
+    // length it covers, L <= 383), the bit-sliced one beyond
     if (o.variant == LABS_VARIANT_AUTO)
         o.variant = have ? tuned.variant
                          : ((minL >= kMfmaAutoLMin && maxL <= kMfmaLMax) ? LABS_VARIANT_MFMA : LABS_VARIANT_BITSLICE);

@@ -86,7 +86,7 @@ hipError_t launch_lds_read_probe(int bytes_per_lane, int blocks, int rounds, uin
 int general_shape_for_length(int L);
 hipError_t launch_general_flip_scores(int L, int count, const uint32_t *x, int32_t *scores, hipStream_t stream);
 constexpr int kMfmaLMax = 383;     // the matrix-core scoring covers every walk length
-constexpr int kMfmaAutoLMin = 129; // below it the bit-sliced scoring is as fast (measured)
+constexpr int kMfmaAutoLMin = 3; // the matrix-core walker was measured faster at every length
 hipError_t launch_flip_scores_mfma(int L, int count, const uint32_t *x, int32_t *scores, hipStream_t stream);
 size_t mfma_wave_lds_bytes(int shape); // per walk (shape < 0: mixed lengths)
 hipError_t launch_walk_general(int shape, WalkState *states, int32_t count, const int32_t *order, uint64_t *tables,

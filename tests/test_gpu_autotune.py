@@ -49,9 +49,16 @@ def test_autotune_single_length(labs, tmp_path, monkeypatch):
     cfgs = [labs.make_cfg(255, SEED, w, steps=700, table_log2=16, trace=(w % 16 == 0)) for w in range(128)]
     opts = _check_against_oracle(labs, cfgs, range(0, 128, 16))
     assert {k: opts[k] for k in TUNED} == {k: best[k] for k in TUNED}
-    # a length of another kernel shape does not take the L = 255 entry
+    # a length of another kernel shape does not take the L = 255 entry: with a later L = 255 entry
+    # of non-default options, L = 255 takes it and L = 101 keeps the untuned defaults
+    with open(cache, "a") as f:
+        f.write(f"{lines[0]} 255 2 8 1 2\n")  # a later entry wins
+    plan = labs.WalkPlan([labs.make_cfg(255, SEED, 0, steps=10)])
+    assert {k: plan.opts()[k] for k in TUNED} == {"variant": 2, "waves_per_block": 8, "probe_width": 1,
+                                                   "persistent": 2}
+    plan.close()
     plan = labs.WalkPlan([labs.make_cfg(101, SEED, 0, steps=10)])
-    assert plan.opts()["variant"] == labs.VARIANT_BITSLICE
+    assert plan.opts()["variant"] == labs.VARIANT_MFMA and plan.opts()["waves_per_block"] == 1
     plan.close()
 
 

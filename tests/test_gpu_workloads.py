@@ -1,5 +1,6 @@
 """The other full-size workloads on the GPU, through the C ABI: the L = 101 batch (1,024 walks x
-10^5 steps) with sampled walks against the oracle, and the uneven batch of every odd L in
+10^5 steps) on the automatic (matrix-core) and the bit-sliced walker with sampled walks against the
+oracle, and the uneven batch of every odd L in
 [201, 303] x 64 walks x 10^6 steps in one launch, checked by properties that hold at any size
 (each walk's best / final ISL is the ISL of its best / final bits, evaluation counts) and by
 invariance under splitting the walks over several launches."""
@@ -23,9 +24,10 @@ def labs():
     return labs
 
 
-def test_l101_batch_full_size(labs):
+@pytest.mark.parametrize("variant", [0, 1])  # automatic (the matrix cores), bit-sliced
+def test_l101_batch_full_size(labs, variant):
     cfgs = [labs.make_cfg(101, SEED, w, steps=100000, table_log2=16) for w in range(1024)]
-    plan = labs.WalkPlan(cfgs)
+    plan = labs.WalkPlan(cfgs, variant=variant)
     plan.run()
     res = plan.results()
     plan.close()
