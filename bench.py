@@ -340,10 +340,12 @@ def best_first(labs, walks=WALKS, steps=1000):
         res, ms = labs.pq_walk_batch(cfg, 64, nlog2)
         evals = sum(r["flip_evals"] for r in res)
         best = np.array([r["best_isl"] for r in res], dtype=np.float64)
+        # the scoring of every iteration runs on the matrix-core walker
+        alg = steps * walks * N * ALG_OPS_PER_FLIP / (ms / 1000.0) / 1e12
         out[name] = {"nbr_table_log2": nlog2, "kernel_ms": ms, "flip_evals": evals,
                      "flip_evals_per_s": evals / (ms / 1000.0),
-                     "alg_ops_frac_of_valu_peak": steps * walks * N * ALG_OPS_PER_FLIP / (ms / 1000.0)
-                     / (VALU_PEAK_TOPS * 1e12),
+                     "roofline": dict(matrix_or_alu_roofline(3, alg), alg_ops_per_flip=ALG_OPS_PER_FLIP,
+                                      note="algorithmic operations of the n flips scored per iteration"),
                      "mean_best_F": float(np.mean(L * L / (2.0 * best))), "max_best_F": float(L * L / (2.0 * best.min()))}
     return out
 

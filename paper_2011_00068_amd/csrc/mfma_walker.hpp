@@ -174,6 +174,9 @@ struct MfmaWalker {
     int32_t bsrc;      // ds_bpermute source of Z: lane 63 - lane
 
     __device__ __forceinline__ int flip(int g) const { return (g < 2 ? 0 : 128) + 2 * lane + (g & 1); }
+    // the lane and the slot g that own flip j
+    __device__ __forceinline__ static int owner_lane(int j) { return (j & 127) >> 1; }
+    __device__ __forceinline__ static int owner_slot(int j) { return (j >> 7) * 2 + (j & 1); }
 
     __device__ __forceinline__ uint32_t *x_lds() const { return lds->xw; }
     __device__ __forceinline__ uint32_t *best_lds() const { return lds->bestx; }

@@ -3,7 +3,8 @@
 // evaluated neighbours that the xLastovka algorithm keeps and impxLast drops (Section 3).
 //
 // One walk per 64-lane wavefront, as the self-avoiding walk: the scoring of the n flips of the
-// current state is the walker's (bit-sliced correlation table).  The queue lives in registers,
+// current state is the walker's (matrix-core or bit-sliced by shape, below; the flips a lane owns
+// follow the walker's mapping: flip(g), owner_lane, owner_slot).  The queue lives in registers,
 // one entry per lane, sorted by (ISL, iteration that generated the entry, flip index): lane 0 is
 // the front, lane q-1 the last of q entries.  Because every entry offered in an iteration was
 // generated after all entries already queued, and the iteration offers its entries in ascending
@@ -23,7 +24,7 @@
 // neighbour, rebuild from its free bits otherwise).
 #include <hip/hip_runtime.h>
 
-#include "walk_impl.hpp"
+#include "mfma_walker.hpp"
 
 namespace liblabs {
 
@@ -37,8 +38,20 @@ __device__ __forceinline__ bool readlane_b(bool v, int l)
     return __builtin_amdgcn_readlane((int)v, l) != 0;
 }
 
-struct WaveLdsPq : WaveLdsBits {
+// the walker's LDS block and the second-table partner list
+template <class Base> struct WaveLdsPqT : Base {
     int16_t nxt[kNMax]; // next higher flip whose neighbours share this flip's second-table slot
+};
+
+// walker per shape: the one-tile matrix-core walker for shapes 2..4 (L = 129..255), the bit-sliced
+// one elsewhere.  The queue's registers next to the walker's set the occupancy: measured on 16,384
+// searches x 1,000 iterations (queue of 64), the matrix cores gain 4 % at L = 201 and 255 and lose
+// 25-27 % at L = 61 and 101 and 6-25 % at L = 303 and 383 (two tiles).
+template <int SHAPE> struct PqWalkerOf {
+    static constexpr bool mfma = SHAPE >= 2 && SHAPE <= 4;
+    using Lds = WaveLdsPqT<typename std::conditional<mfma, WaveLdsMfma, WaveLdsBits>::type>;
+    using type = typename std::conditional<mfma, MfmaWalker<ShapeGK<SHAPE>::KW, false, Lds>,
+                                           Walker<ShapeGK<SHAPE>::G, ShapeGK<SHAPE>::KW, false>>::type;
 };
 
 __device__ __forceinline__ int32_t wave_shr1(int32_t v)
@@ -116,12 +129,12 @@ struct Queue {
     }
 };
 
-template <int G, int KW>
+template <class W, class PqLds>
 __device__ __forceinline__ void run_pq(WalkState *__restrict__ wsp, uint64_t *__restrict__ tables,
                                        uint64_t *__restrict__ N, int nlog2, int cap, int32_t *__restrict__ trace,
-                                       int32_t *__restrict__ scores, WaveLdsPq *lds, const uint64_t *zk)
+                                       int32_t *__restrict__ scores, PqLds *lds, const uint64_t *zk)
 {
-    using W = Walker<G, KW, false>;
+    constexpr int G = W::kG;
     int lane = lane_id();
     asm volatile("" : "+v"(lane));
     WalkState &ws = *wsp;
@@ -154,7 +167,7 @@ __device__ __forceinline__ void run_pq(WalkState *__restrict__ wsp, uint64_t *__
     int32_t nxt0[G];
 #pragma unroll
     for (int g = 0; g < G; g++) {
-        const int j = lane + 64 * g;
+        const int j = w.flip(g);
         int p = -1;
         if (nbr && !nexact && j < n) {
             const uint64_t sj = zk[j] >> (64 - nlog2);
@@ -221,7 +234,7 @@ __device__ __forceinline__ void run_pq(WalkState *__restrict__ wsp, uint64_t *__
         if (scp) {
 #pragma unroll
             for (int g = 0; g < G; g++) {
-                const int j = w.lane + 64 * g;
+                const int j = w.flip(g);
                 if (j < n)
                     scp[j] = isl_j[g];
             }
@@ -240,7 +253,7 @@ __device__ __forceinline__ void run_pq(WalkState *__restrict__ wsp, uint64_t *__
         int skipped = 0;
 #pragma unroll
         for (int g = 0; g < G; g++) {
-            const int j = w.lane + 64 * g;
+            const int j = w.flip(g);
             const bool valid = j < n;
             const int jj = valid ? j : 0;
             hn[g] = w.h ^ zk[jj];
@@ -275,12 +288,12 @@ __device__ __forceinline__ void run_pq(WalkState *__restrict__ wsp, uint64_t *__
                         uint64_t m = M[0];
 #pragma unroll
                         for (int g2 = 1; g2 < G; g2++)
-                            m = ((p >> 6) == g2) ? M[g2] : m;
-                        later = ((m >> (p & 63)) & 1ull) != 0ull;
+                            m = (W::owner_slot(p) == g2) ? M[g2] : m;
+                        later = ((m >> W::owner_lane(p)) & 1ull) != 0ull;
                         p = lds->nxt[p];
                     }
                     if (!later) {
-                        const int j = w.lane + 64 * g;
+                        const int j = w.flip(g);
                         uint32_t x0 = w.x[0];
                         if (j < 32)
                             x0 ^= 1u << j;
@@ -306,10 +319,10 @@ __device__ __forceinline__ void run_pq(WalkState *__restrict__ wsp, uint64_t *__
             bool kn = false, vis = false;
 #pragma unroll
             for (int g = 0; g < G; g++) {
-                kn = (w.lane + 64 * g == jn) ? known[g] : kn;
-                vis = (w.lane + 64 * g == jn) ? visited[g] : vis;
+                kn = (w.flip(g) == jn) ? known[g] : kn;
+                vis = (w.flip(g) == jn) ? visited[g] : vis;
             }
-            const int owner = jn & 63;
+            const int owner = W::owner_lane(jn);
             if (!readlane_b(kn, owner)) {
                 // probe the kPqProbe smallest unprobed candidates together
                 uint32_t uk[G];
@@ -331,7 +344,7 @@ __device__ __forceinline__ void run_pq(WalkState *__restrict__ wsp, uint64_t *__
                         break;
 #pragma unroll
                     for (int g = 0; g < G; g++) {
-                        const bool me = w.lane + 64 * g == (int)(u & 255u);
+                        const bool me = w.flip(g) == (int)(u & 255u);
                         sel[g] = sel[g] || me;
                         uk[g] = me ? 0xFFFFFFFFu : uk[g];
                     }
@@ -345,12 +358,12 @@ __device__ __forceinline__ void run_pq(WalkState *__restrict__ wsp, uint64_t *__
                 }
 #pragma unroll
                 for (int g = 0; g < G; g++)
-                    vis = (w.lane + 64 * g == jn) ? visited[g] : vis;
+                    vis = (w.flip(g) == jn) ? visited[g] : vis;
             }
             if (readlane_b(vis, owner)) {
 #pragma unroll
                 for (int g = 0; g < G; g++)
-                    cand[g] = (w.lane + 64 * g == jn) ? 0xFFFFFFFFu : cand[g];
+                    cand[g] = (w.flip(g) == jn) ? 0xFFFFFFFFu : cand[g];
                 continue;
             }
             uint32_t nx[kXWords];
@@ -372,7 +385,7 @@ __device__ __forceinline__ void run_pq(WalkState *__restrict__ wsp, uint64_t *__
             q = min(q + 1, cap);
 #pragma unroll
             for (int g = 0; g < G; g++)
-                cand[g] = (w.lane + 64 * g == jn) ? 0xFFFFFFFFu : cand[g];
+                cand[g] = (w.flip(g) == jn) ? 0xFFFFFFFFu : cand[g];
         }
         // entries past the capacity are not part of the queue
         if (w.lane >= cap)
@@ -508,15 +521,16 @@ __global__ void __launch_bounds__(64) k_pq_walk(WalkState *__restrict__ states, 
                                                 uint64_t *__restrict__ nbr_tables, int nlog2, int cap,
                                                 int32_t *__restrict__ trace, int32_t *__restrict__ scores)
 {
+    using W = typename PqWalkerOf<SHAPE>::type;
     __shared__ uint64_t zk[kNMax];
-    __shared__ WaveLdsPq lds;
+    __shared__ typename PqWalkerOf<SHAPE>::Lds lds;
     fill_zobrist(zk);
     const int idx = (int)blockIdx.x;
     if (idx >= count)
         return;
     const int wi = order[idx];
     uint64_t *N = nlog2 > 0 ? nbr_tables + ((int64_t)wi << nlog2) : nullptr;
-    run_pq<ShapeGK<SHAPE>::G, ShapeGK<SHAPE>::KW>(&states[wi], tables, N, nlog2, cap, trace, scores, &lds, zk);
+    run_pq<W>(&states[wi], tables, N, nlog2, cap, trace, scores, &lds, zk);
 }
 
 } // namespace

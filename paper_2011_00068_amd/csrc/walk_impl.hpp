@@ -149,6 +149,9 @@ struct Walker {
 
     // flip scored in slot g of this lane
     __device__ __forceinline__ int flip(int g) const { return lane + 64 * g; }
+    // the lane and the slot g that own flip j
+    __device__ __forceinline__ static int owner_lane(int j) { return j & 63; }
+    __device__ __forceinline__ static int owner_slot(int j) { return j >> 6; }
 
     // LDS copies of the current and of the best free bits
     __device__ __forceinline__ uint32_t *x_lds() const { return lds->xw; }
