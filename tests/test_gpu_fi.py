@@ -1,7 +1,7 @@
 """GPU parity of the first-improvement search with perturbations (labs_fi_walk_batch; the method
 of Dimitrov et al. described in Section 2) against the oracle, through the C ABI: full traces
 (move or perturbation, ISL per step), every step's flip scores and the per-walk results, bit for
-bit, at every kernel shape (bit-sliced scoring below L = 129, matrix cores from there), with
+bit, at every kernel shape (matrix-core scoring at every length), with
 restarts, targets, watch levels and perturbation sizes from 1 to 32 symbols."""
 import numpy as np
 import pytest
