@@ -524,6 +524,8 @@ extern "C" int labs_walk_plan_create(int32_t n_walks, const labs_walk_cfg *cfg, 
     if (e == hipSuccess) e = hipMalloc(&p->d_counter, sizeof(int32_t));
     if (e == hipSuccess) e = hipMalloc(&p->d_order, sizeof(int32_t) * (size_t)n_walks);
     if (e == hipSuccess) e = hipMemcpy(p->d_pristine, p->pristine.data(), sizeof(WalkState) * (size_t)n_walks, hipMemcpyHostToDevice);
+    // the states too: their table epochs (0: the tables' contents are unknown) carry over runs
+    if (e == hipSuccess) e = hipMemcpy(p->d_states, p->pristine.data(), sizeof(WalkState) * (size_t)n_walks, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_order, order.data(), sizeof(int32_t) * (size_t)n_walks, hipMemcpyHostToDevice);
     if (e == hipSuccess && p->d_trace) e = hipMemset(p->d_trace, 0, sizeof(int32_t) * 2 * (size_t)p->trace_records);
     if (e == hipSuccess && p->d_scores) e = hipMemset(p->d_scores, 0, sizeof(int32_t) * (size_t)p->score_entries);

@@ -44,7 +44,7 @@ struct alignas(16) WalkState {
     int32_t restarts;
     int32_t traps;
     int32_t status;
-    int32_t pad0;
+    int32_t table_epoch; // epoch of the visited table's entries, 0 = contents unknown
     uint32_t x[kXWords];
     uint32_t best_x[kXWords];
 };

@@ -542,6 +542,34 @@ __device__ inline uint64_t slot_of(uint64_t hh, uint32_t x0, bool exact, int log
     return exact ? (uint64_t)x0 : (hh >> (64 - log2));
 }
 
+// Table epochs.  A walk's table holds the entries of its current start (or restart) and stale
+// ones of earlier starts; an entry written during epoch e is the word (h | 1) ^ (e << (64 - log2)),
+// i.e. the state's entry with the epoch XORed into its top log2 bits.  A probe during epoch e
+// compares with the same form, so a stale entry (epoch e' != e) can never match: in a hashed
+// table the top log2 bits of h are the slot, equal for every state stored there, so the two words
+// differ in e ^ e' there; in a table addressed by the free bits, a slot holds a single state and
+// the words again differ in e ^ e'.  Nor does a cleared word (0) match: bit 0 of every expected
+// word is set.  So a
+// probe answers as it would in a table cleared at the start, and a start only takes the next
+// epoch; the 2^log2 words are cleared when the epochs 1 .. 2^log2 - 1 have all been used, and
+// when the table's contents are unknown (epoch 0: a walk state that has never run on it).  The
+// slot comes from the hash alone; a probe XORs the tag into the word it expects while its load is
+// in flight.
+__device__ inline uint64_t epoch_tag(uint32_t ep, int log2)
+{
+    return (uint64_t)ep << (64 - log2);
+}
+
+// The epoch of a new start after epoch ep (clearing the table when none is left).
+__device__ inline uint32_t next_epoch(uint64_t *T, int log2, uint32_t ep)
+{
+    if (ep == 0u || ep >= (1u << log2) - 1u) {
+        clear_table(T, log2);
+        return 1u;
+    }
+    return ep + 1u;
+}
+
 // ---------------------------------------------------------------------------------------------
 // One walk, advanced until its budget, its target, or the launch's step limit.
 // ---------------------------------------------------------------------------------------------
@@ -578,6 +606,8 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
     const int64_t target = su(ws.target_isl);
     const int64_t watch = su(ws.watch_isl);
     uint64_t *T = tables + su(ws.table_offset);
+    uint32_t ep = (uint32_t)su(ws.table_epoch); // the table's epoch (epoch_tag above)
+    uint64_t tag = 0;
     const int64_t trace_off = su(ws.trace_offset);
     const int64_t score_off = su(ws.score_offset);
 
@@ -591,10 +621,11 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
     if (status0 == kFresh) {
         restart_idx = 0;
         start_bits(seed, walk_id, 0u, n, w.x);
-        clear_table(T, tlog2);
+        ep = next_epoch(T, tlog2, ep);
+        tag = epoch_tag(ep, tlog2);
         w.rebuild();
         if (lane == 0)
-            T[slot_of(w.h, w.x0, exact, tlog2)] = w.h | 1ull;
+            T[slot_of(w.h, w.x0, exact, tlog2)] = (w.h | 1ull) ^ tag;
         t = 0;
         flips = 0;
         restarts = 0;
@@ -620,6 +651,7 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
         wstep = su(ws.watch_step);
         best_isl = su(ws.best_isl);
         best_step = su(ws.best_step);
+        tag = epoch_tag(ep, tlog2);
         w.rebuild();
     }
 
@@ -717,12 +749,18 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
             restarts++;
             restart_idx++;
             start_bits(seed, walk_id, (uint32_t)restart_idx, n, w.x);
-            clear_table(T, tlog2);
+            // The last step's store: after a trap, the word for hash 0 at the slot of the state
+            // the trap moved to, which is not that state's entry; cleared (by the lanes that
+            // stored it) so that no later epoch can meet it.  Otherwise an entry of the ending
+            // epoch, which no probe can match any more anyway.
+            T[slot_cur] = 0ull;
+            ep = next_epoch(T, tlog2, ep);
+            tag = epoch_tag(ep, tlog2);
             w.rebuild();
             slot_cur = (uint32_t)slot_of(w.h, w.x0, exact, tlog2);
             jskip = -1;
             if (lane == 0)
-                T[slot_cur] = w.h | 1ull;
+                T[slot_cur] = (w.h | 1ull) ^ tag;
             if (TRACE && trap_trp && lane == 0) {
                 trap_trp[0] = -1;
                 trap_trp[1] = w.isl;
@@ -792,7 +830,7 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
 #pragma unroll
                 for (int i = 0; i < PW; i++)
                     pmask |= cand[i] != 0xFFFFFFFFu ? 1ull << i : 0ull;
-                const uint64_t okmask = ballot(got != (hc | 1ull)) & pmask;
+                const uint64_t okmask = ballot(got != ((hc | 1ull) ^ tag)) & pmask;
                 if (okmask != 0ull) {
                     const int first = __builtin_ctzll(okmask);
                     uint32_t pick = cand[0];
@@ -823,9 +861,9 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
             ts++;
             rem--;
             // Trapped (every flip leads to a visited state): the walk restarts, which rebuilds all
-            // of the walker's state and clears its table, so committing any flip first (flip 0)
-            // is harmless; the step then takes one path whether or not it trapped.  The trap's
-            // table store is overwritten by the clear (the same lanes store there first).
+            // of the walker's state and empties its table (the next epoch), so committing any flip
+            // first (flip 0) is harmless; the step then takes one path whether or not it trapped.
+            // The trap's table store (hash 0) is cleared by the restart.
             const bool trapped = js < 0;
             js = trapped ? 0 : js;
             w.template commit<false>(js, isl_new);
@@ -837,7 +875,7 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
                 // formed on the vector unit (one 64-bit shift-add instead of four scalar ops)
                 uint32_t sv = s_new;
                 asm volatile("" : "+v"(sv));
-                T[sv] = w.h | 1ull;
+                T[sv] = (w.h | 1ull) ^ tag;
                 jskip = s_new != slot_cur ? js : -1;
                 slot_cur = s_new;
             }
@@ -889,6 +927,7 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
         ws.best_isl = best_isl;
         ws.best_step = best_step;
         ws.h = w.h;
+        ws.table_epoch = (int32_t)ep;
         ws.isl = w.isl;
         ws.restart_idx = restart_idx;
         ws.restarts = restarts;

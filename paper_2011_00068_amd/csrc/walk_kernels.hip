@@ -19,8 +19,13 @@ __global__ void k_reset(WalkState *__restrict__ states, const WalkState *__restr
                         int32_t n_walks, int32_t *__restrict__ counter)
 {
     const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (i < n_walks)
+    if (i < n_walks) {
+        // a run starts its walks afresh on the tables of the previous run: the table epochs
+        // carry over, so that a start takes the next epoch instead of clearing the table
+        const int32_t ep = states[i].table_epoch;
         states[i] = pristine[i];
+        states[i].table_epoch = ep;
+    }
     if (i == 0 && counter)
         *counter = 0;
 }

@@ -54,6 +54,33 @@ def test_l31_single_walk_full_trajectory(labs, variant):
     assert g["best_isl"] == 79  # the enumerated skew optimum
 
 
+@pytest.mark.parametrize("variant", [1, 2, 3], ids=["bitslice", "direct", "mfma"])
+def test_plan_reruns_reuse_tables(labs, variant):
+    # A plan's runs reuse its visited tables without clearing them: every start and restart takes
+    # the table's next epoch, and a table is cleared only on its first use or when its epochs run
+    # out (3 for a 2^2-word table, 7 for 2^3).  Six runs in a row, with restarts and traps, in
+    # hashed tables and in tables addressed by the free bits (L = 3, 31, 41): each equals the
+    # oracle, whose table is cleared at every start.
+    cfgs = [labs.make_cfg(255, SEED, 0, steps=400, table_log2=2, restart_period=37, trace=True),
+            labs.make_cfg(3, SEED, 1, steps=60, table_log2=2, restart_period=7, trace=True),
+            labs.make_cfg(5, SEED, 2, steps=80, table_log2=2, trace=True),
+            labs.make_cfg(13, SEED, 3, steps=300, table_log2=3, trace=True),
+            labs.make_cfg(101, SEED, 4, steps=300, table_log2=3, restart_period=50, trace=True),
+            labs.make_cfg(31, SEED, 5, steps=2000, table_log2=16, restart_period=300, trace=True),
+            labs.make_cfg(41, SEED, 6, steps=1500, table_log2=21, restart_period=200, trace=True),
+            labs.make_cfg(7, SEED, 7, steps=200, table_log2=4, trace=True),
+            labs.make_cfg(13, SEED, 8, steps=600, table_log2=7, trace=True),
+            labs.make_cfg(21, SEED, 9, steps=3000, table_log2=11, trace=True)]
+    refs = [oracle_walk(c, trace=True) for c in cfgs]
+    assert sum(r["traps"] for r in refs) >= 30
+    plan = labs.WalkPlan(cfgs, variant=variant)
+    for run in range(6):
+        plan.run()
+        for i, (g, r) in enumerate(zip(plan.results(), refs)):
+            assert_same(g, r, f"run {run}, L = {cfgs[i].L}")
+    plan.close()
+
+
 @pytest.mark.parametrize("L", [3, 5, 7, 9, 13, 33, 63, 65, 95, 97, 101, 127, 129, 131, 191, 193, 201,
                                255, 257, 259, 303, 321, 383])
 def test_short_walks_every_shape(labs, L):
