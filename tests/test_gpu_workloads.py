@@ -26,11 +26,15 @@ def labs():
 
 @pytest.mark.parametrize("variant", [0, 1])  # automatic (the matrix cores), bit-sliced
 def test_l101_batch_full_size(labs, variant):
+    # (two runs of the plan, as bench.py times it: the second reuses the tables under new epochs)
     cfgs = [labs.make_cfg(101, SEED, w, steps=100000, table_log2=16) for w in range(1024)]
     plan = labs.WalkPlan(cfgs, variant=variant)
     plan.run()
+    first = plan.results()
+    plan.run()
     res = plan.results()
     plan.close()
+    assert res == first
     for w in (0, 513):
         r = o.walk(101, SEED, w, steps=100000, table_log2=16)
         for k in ("best_isl", "best_step", "final_isl", "best_bits", "final_bits", "restarts", "traps", "flip_evals"):
@@ -78,7 +82,8 @@ def test_uneven_batch_long_walks_match_oracle(labs):
     # The uneven batch's launch (all 52 lengths x 64 walks in one grid of the mixed-length
     # matrix-core kernel, replayed from a hipGraph) run for 2 x 10^5 steps, past the point where
     # the 2^16-word visited tables start to evict; three of its walks (shortest, headline and
-    # longest length) compared with the oracle in every result field.
+    # longest length) compared with the oracle in every result field, from the graph's second
+    # replay (tables reused under new epochs), which equals the first.
     from concurrent.futures import ThreadPoolExecutor
 
     steps = 200000
@@ -87,9 +92,12 @@ def test_uneven_batch_long_walks_match_oracle(labs):
     plan = labs.WalkPlan(cfgs, use_graph=True)
     assert plan.opts()["variant"] == labs.VARIANT_MFMA
     plan.run()
+    first = plan.results()
+    plan.run()
     res = plan.results()
     _, launches = plan.last_timing()
     plan.close()
+    assert res == first
     assert launches == 1
     picks = [(201, 0), (255, 17), (303, 63)]
     with ThreadPoolExecutor(max_workers=len(picks)) as ex:
