@@ -587,9 +587,11 @@ struct MfmaWalker {
         // = c) in the +-1 byte strings: kind p at byte a, kind 2+p at byte 63 - a (when a <= 63; a
         // dummy word otherwise), kind 4+p at byte 127 - a, each written with its new value; the
         // parity bit strings are rebuilt at the next (re)start.  No byte read above is written here
-        // (the one at the mirror is the excluded shift, whose value is not used).
-        if (lane < 2) {
-            // (per-lane values by v_writelane: lane 0's replaces lane 1's, no compare and select)
+        // (the one at the mirror is the excluded shift, whose value is not used).  Every lane
+        // writes: lanes 2..63 repeat lane 1's byte (the same address and value), which costs no
+        // exec mask around the writes.
+        {
+            // (per-lane values by v_writelane: lane 0's replaces the others', no compare and select)
             const int a = write_lane<0>(nps, hjs);
             const int32_t v = write_lane<0>(-emir * sjs, -sjs);
             *(lds_i8 *)(uintptr_t)(sp_a + (uint32_t)a) = (int8_t)v;

@@ -555,9 +555,10 @@ __device__ inline uint64_t slot_of(uint64_t hh, uint32_t x0, bool exact, int log
 // when the table's contents are unknown (epoch 0: a walk state that has never run on it).  The
 // slot comes from the hash alone; a probe XORs the tag into the word it expects while its load is
 // in flight.
-__device__ inline uint64_t epoch_tag(uint32_t ep, int log2)
+// The high word of the tag e << (64 - log2) (its low word is 0: log2 <= 30).
+__device__ inline uint32_t epoch_tag_hi(uint32_t ep, int log2)
 {
-    return (uint64_t)ep << (64 - log2);
+    return ep << (32 - log2);
 }
 
 // The epoch of a new start after epoch ep (clearing the table when none is left).
@@ -606,8 +607,8 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
     const int64_t target = su(ws.target_isl);
     const int64_t watch = su(ws.watch_isl);
     uint64_t *T = tables + su(ws.table_offset);
-    uint32_t ep = (uint32_t)su(ws.table_epoch); // the table's epoch (epoch_tag above)
-    uint64_t tag = 0;
+    uint32_t ep = (uint32_t)su(ws.table_epoch); // the table's epoch (see epoch_tag_hi)
+    uint32_t tag_hi = 0;
     const int64_t trace_off = su(ws.trace_offset);
     const int64_t score_off = su(ws.score_offset);
 
@@ -622,10 +623,10 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
         restart_idx = 0;
         start_bits(seed, walk_id, 0u, n, w.x);
         ep = next_epoch(T, tlog2, ep);
-        tag = epoch_tag(ep, tlog2);
+        tag_hi = epoch_tag_hi(ep, tlog2);
         w.rebuild();
         if (lane == 0)
-            T[slot_of(w.h, w.x0, exact, tlog2)] = (w.h | 1ull) ^ tag;
+            T[slot_of(w.h, w.x0, exact, tlog2)] = (w.h | 1ull) ^ ((uint64_t)tag_hi << 32);
         t = 0;
         flips = 0;
         restarts = 0;
@@ -651,7 +652,7 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
         wstep = su(ws.watch_step);
         best_isl = su(ws.best_isl);
         best_step = su(ws.best_step);
-        tag = epoch_tag(ep, tlog2);
+        tag_hi = epoch_tag_hi(ep, tlog2);
         w.rebuild();
     }
 
@@ -755,12 +756,12 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
             // epoch, which no probe can match any more anyway.
             T[slot_cur] = 0ull;
             ep = next_epoch(T, tlog2, ep);
-            tag = epoch_tag(ep, tlog2);
+            tag_hi = epoch_tag_hi(ep, tlog2);
             w.rebuild();
             slot_cur = (uint32_t)slot_of(w.h, w.x0, exact, tlog2);
             jskip = -1;
             if (lane == 0)
-                T[slot_cur] = (w.h | 1ull) ^ tag;
+                T[slot_cur] = (w.h | 1ull) ^ ((uint64_t)tag_hi << 32);
             if (TRACE && trap_trp && lane == 0) {
                 trap_trp[0] = -1;
                 trap_trp[1] = w.isl;
@@ -830,7 +831,7 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
 #pragma unroll
                 for (int i = 0; i < PW; i++)
                     pmask |= cand[i] != 0xFFFFFFFFu ? 1ull << i : 0ull;
-                const uint64_t okmask = ballot(got != ((hc | 1ull) ^ tag)) & pmask;
+                const uint64_t okmask = ballot(got != ((hc | 1ull) ^ ((uint64_t)tag_hi << 32))) & pmask;
                 if (okmask != 0ull) {
                     const int first = __builtin_ctzll(okmask);
                     uint32_t pick = cand[0];
@@ -875,7 +876,7 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
                 // formed on the vector unit (one 64-bit shift-add instead of four scalar ops)
                 uint32_t sv = s_new;
                 asm volatile("" : "+v"(sv));
-                T[sv] = (w.h | 1ull) ^ tag;
+                T[sv] = (w.h | 1ull) ^ ((uint64_t)tag_hi << 32);
                 jskip = s_new != slot_cur ? js : -1;
                 slot_cur = s_new;
             }
