@@ -673,8 +673,10 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
     int32_t rem = (R > 0) ? (int32_t)min<int64_t>((t0 / R + 1) * R - t0, INT32_MAX) : INT32_MAX;
     const bool hit_found0 = hit >= 0;
     const bool watch_found0 = wstep >= 0;
-    // The step loop runs while ts < lim; reaching the target sets lim = -1 (stopped).
+    // The step loop runs while ts < lim; reaching the target sets lim = -1 (stopped).  The inner
+    // loop below runs to lim_in, the earlier of lim and the next periodic restart.
     int32_t lim = (tgt >= 0 && hit_found0) ? -1 : nsteps;
+    int32_t lim_in = lim;
     // A committed state needs bookkeeping only if its ISL is at most thr: a new best, or the target
     // or watch level not reached before.  That bookkeeping (rarely updated) lives in LDS, so the
     // step loop carries only thr and lim: book[0] best ISL, [1] its step in this launch, [2] / [3]
@@ -711,6 +713,7 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
         hf |= nh ? 1 : 0;
         wf |= nw ? 1 : 0;
         lim = nh ? -1 : lim;
+        lim_in = nh ? -1 : lim_in;
         thr = su(threshold(best, hf != 0, wf != 0));
         if (nb) {
             w.sync_x_lds();
@@ -772,8 +775,13 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
                 note_state(ts);
         }
         // One exit, at the bottom: with a second exit (a break) the compiler copies every
-        // loop-carried register once per step on the way back to the top.
-        if (ts < lim) do {
+        // loop-carried register once per step on the way back to the top.  The loop ends at a
+        // trap, at lim or at the next periodic restart (rem steps away), so that the restart
+        // countdown and the trap count are settled once per inner loop, not per step.
+        lim_in = rem < lim - ts ? ts + rem : lim;
+        const int32_t ts_in = ts;
+        bool trapped = false;
+        if (ts < lim_in) do {
             // Keep per-lane index arithmetic inside the loop instead of pinning ~100 VGPRs of
             // loop invariants for the whole walk: the values are cheap to recompute and the
             // registers are worth more as occupancy.
@@ -860,12 +868,11 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
             }
 
             ts++;
-            rem--;
             // Trapped (every flip leads to a visited state): the walk restarts, which rebuilds all
             // of the walker's state and empties its table (the next epoch), so committing any flip
             // first (flip 0) is harmless; the step then takes one path whether or not it trapped.
             // The trap's table store (hash 0) is cleared by the restart.
-            const bool trapped = js < 0;
+            trapped = js < 0;
             js = trapped ? 0 : js;
             w.template commit<false>(js, isl_new);
             w.h = h_new;
@@ -891,14 +898,15 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
             }
             if (TRACE && scp)
                 scp += n;
-            traps += trapped ? 1 : 0;
             if (!trapped && w.isl <= thr)
                 note_state(ts);
-            // a restart after a trap, or the periodic one (not after the last step, not once
-            // stopped); a trap replaces a periodic restart due at the same step
-            need_restart = trapped || (rem == 0 && ts < left32 && lim >= 0);
-            rem = rem == 0 ? R32 : rem;
-        } while (!need_restart && ts < lim);
+        } while (!trapped && ts < lim_in);
+        traps += trapped ? 1 : 0;
+        rem -= ts - ts_in;
+        // a restart after a trap, or the periodic one (not after the last step, not once
+        // stopped); a trap replaces a periodic restart due at the same step
+        need_restart = trapped || (rem == 0 && ts < left32 && lim >= 0);
+        rem = rem == 0 ? R32 : rem;
         if (!need_restart)
             break;
     }
