@@ -780,7 +780,7 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
         // countdown and the trap count are settled once per inner loop, not per step.
         lim_in = rem < lim - ts ? ts + rem : lim;
         const int32_t ts_in = ts;
-        bool trapped = false;
+        int32_t trapped = 0; // 1 after a trap (which ends the inner loop)
         if (ts < lim_in) do {
             // Keep per-lane index arithmetic inside the loop instead of pinning ~100 VGPRs of
             // loop invariants for the whole walk: the values are cheap to recompute and the
@@ -800,7 +800,7 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
 
             // best non-visited flip: take the PW smallest keys, probe them together
             int js = -1;
-            int32_t isl_new = 0;
+            int32_t isl_new = INT32_MAX; // (a trap's: above every threshold)
             uint64_t h_new = 0; // hash of the chosen neighbour (from its probe)
             static_assert(PW >= 1 && PW <= 2, "one or two candidates per probe round");
             uint32_t cand[PW];
@@ -871,9 +871,11 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
             // Trapped (every flip leads to a visited state): the walk restarts, which rebuilds all
             // of the walker's state and empties its table (the next epoch), so committing any flip
             // first (flip 0) is harmless; the step then takes one path whether or not it trapped.
-            // The trap's table store (hash 0) is cleared by the restart.
-            trapped = js < 0;
-            js = trapped ? 0 : js;
+            // The trap's table store (hash 0) is cleared by the restart, and its ISL (INT32_MAX)
+            // passes no threshold.  A trap also ends the inner loop (lim_in = ts).
+            trapped = (int32_t)((uint32_t)js >> 31);
+            lim_in = js < 0 ? ts : lim_in;
+            js = max(js, 0);
             w.template commit<false>(js, isl_new);
             w.h = h_new;
             {
@@ -898,10 +900,10 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
             }
             if (TRACE && scp)
                 scp += n;
-            if (!trapped && w.isl <= thr)
+            if (w.isl <= thr)
                 note_state(ts);
-        } while (!trapped && ts < lim_in);
-        traps += trapped ? 1 : 0;
+        } while (ts < lim_in);
+        traps += trapped;
         rem -= ts - ts_in;
         // a restart after a trap, or the periodic one (not after the last step, not once
         // stopped); a trap replaces a periodic restart due at the same step
