@@ -520,9 +520,15 @@ struct MfmaWalker {
         const int slot = BIG ? (js >> 7) * 2 + (js & 1) : js & 1;
         // mult of js at its owner lane: -8 s_js, or -4 s_c at the centre
         int32_t mj = __builtin_amdgcn_readlane(mult[0], ol);
+        if constexpr (G == 2) {
+            // both slots' values, then one scalar select (left to itself the compiler branches)
+            const int32_t m1 = __builtin_amdgcn_readlane(mult[1], ol);
+            asm("s_cmp_eq_u32 %1, 0\n\ts_cselect_b32 %0, %2, %3" : "=s"(mj) : "s"(slot), "s"(mj), "s"(m1) : "scc");
+        } else {
 #pragma unroll
-        for (int g = 1; g < G; g++)
-            mj = slot == g ? __builtin_amdgcn_readlane(mult[g], ol) : mj;
+            for (int g = 1; g < G; g++)
+                mj = slot == g ? __builtin_amdgcn_readlane(mult[g], ol) : mj;
+        }
         const int32_t f = mj >> 1;                   // -4 s_js (-2 s_c at the centre)
         const int32_t sjs = ~((mj >> 31) << 1);      // s_js before the commit: -1 if mj > 0, else 1
         const int hjs = js >> 1;
