@@ -150,6 +150,10 @@ struct MfmaWalker {
     static constexpr int kG = G;
     static constexpr int QR = (KW + 1) / 2;
     static constexpr int KB = (32 * KW + 16 + 63) / 64; // K blocks of 64
+    // K blocks of the second tile (BIG): its Y terms at half index 64 + h need t = kappa + 1 + nn
+    // <= c - 64 <= 127 (the string is 0 past the sequence), its Z terms at half index h' <= c / 2
+    // need t <= h' + 15 <= 111, so two blocks hold every term of an existing flip
+    static constexpr int KB2 = KB < 2 ? KB : 2;
     static constexpr int kCBytes = 4 * LdsT::kCDwords;  // distance of the C' copies
     using Lds = LdsT;
     static_assert(!BIG || LdsT::kStrings == 6, "the second tile needs the big layout");
@@ -445,38 +449,40 @@ struct MfmaWalker {
         }
     }
 
-    // One K-sweep of a tile (A operand at LDS address a_addr) with the C' bytes now in the
-    // copies.
+    // One K-sweep of a tile (A operand at LDS address a_addr, NKB blocks) with the C' bytes now
+    // in the copies.
+    template <int NKB>
     __device__ __forceinline__ mfma_v4i tile(uint32_t a_addr) const
     {
         // A windows start on 16-byte boundaries (one 16-byte read), B windows on dword boundaries
         const lds_cv4 *ap4 = (const lds_cv4 *)(uintptr_t)a_addr;
         const lds_cu32 *bp = (const lds_cu32 *)(uintptr_t)tb;
         // every operand load first, so that one LDS latency covers the whole K sweep
-        mfma_v4i a[KB], b[KB];
+        mfma_v4i a[NKB], b[NKB];
 #pragma unroll
-        for (int kb = 0; kb < KB; kb++) {
+        for (int kb = 0; kb < NKB; kb++) {
             a[kb] = ap4[4 * kb];
             b[kb] = mfma_v4i{(int)bp[16 * kb], (int)bp[16 * kb + 1], (int)bp[16 * kb + 2], (int)bp[16 * kb + 3]};
         }
         mfma_v4i acc = {0, 0, 0, 0};
 #pragma unroll
-        for (int kb = 0; kb < KB; kb++)
+        for (int kb = 0; kb < NKB; kb++)
             acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[kb], b[kb], acc, 0, 0, 0);
         return acc;
     }
 
     // the product of a tile, with the second sweep of a wide C' (C' = 64 hi + lo)
+    template <int NKB = KB>
     __device__ __forceinline__ mfma_v4i tile_all(uint32_t a_addr)
     {
-        mfma_v4i d = tile(a_addr);
+        mfma_v4i d = tile<NKB>(a_addr);
         if (planes > 8) {
             // the copies held lo (the caller rewrites them with lo again afterwards when several
             // tiles use them); the wave's LDS operations run in order, so the reads above complete
             // before the hi bytes overwrite them
             put_c(2);
             lds_fence();
-            const mfma_v4i hi = tile(a_addr);
+            const mfma_v4i hi = tile<NKB>(a_addr);
             d = d + hi * 64;
         }
         return d;
@@ -502,7 +508,7 @@ struct MfmaWalker {
         if constexpr (BIG) {
             if (planes > 8) // the copies hold hi now: lo again for the second tile
                 put_c(1);
-            const mfma_v4i d2 = tile_all(ta2);
+            const mfma_v4i d2 = tile_all<KB2>(ta2);
             // second tile: Y for half index 64 + lane, Z for 127 - lane (brought from lane 63 - lane)
             isl_j[2] = mad24(mult[2], d2[0] + __builtin_amdgcn_ds_bpermute(bsrc, d2[2]), base[2]);
             isl_j[3] = mad24(mult[3], d2[1] + __builtin_amdgcn_ds_bpermute(bsrc, d2[3]), base[3]);
