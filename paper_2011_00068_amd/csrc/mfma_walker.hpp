@@ -24,7 +24,8 @@
 // so D[r][nn] = sum_t A B is Y (kind p) at h and Z (kind 2+p) at 63 - h.  Every A row is an
 // aligned 16-byte window of a byte copy of one string; every B column is a 16-byte window of C'
 // starting at byte t0 - 1 - nn, read from whichever of four copies of C' shifted by 0..3 bytes
-// puts it on a dword boundary (each step writes C' into all four).  K = 64 KB covers t <= c + 15.
+// puts it on a dword boundary (each step writes C' into all four).  K = 64 KB covers every t of a
+// nonzero term, t <= c (see KB below).
 // C' fits int8 unless |C_k| > 127; then C' = 64 hi + lo (lo in 0..63, hi in -4..3) and a second
 // pass adds 64 x the hi tile.  Lane layout of the instruction (checked on gfx950): lane l holds
 // row / column l % 16 of A / B and K slice 16 (l / 16) .. +15 in its four registers' bytes, and D
@@ -149,7 +150,12 @@ struct MfmaWalker {
     static constexpr int G = BIG ? 4 : 2;
     static constexpr int kG = G;
     static constexpr int QR = (KW + 1) / 2;
-    static constexpr int KB = (32 * KW + 16 + 63) / 64; // K blocks of 64
+    // K blocks of 64: a tile's Y term at half index h reads s^p at h + 1 + kappa = h + t - nn <= c
+    // (the string is 0 past the sequence; h >= nn), so t <= c; its Z term at 63 - h reads s^p at
+    // 63 - 16 i - t >= 0, so t <= 63.  Every nonzero term has t <= the largest c of the walker
+    // (127 with one tile, 191 with two).
+    static constexpr int kCMaxW = BIG ? (32 * KW < 191 ? 32 * KW : 191) : (32 * KW < 127 ? 32 * KW : 127);
+    static constexpr int KB = (kCMaxW + 64) / 64;
     // K blocks of the second tile (BIG): its Y terms at half index 64 + h need t = kappa + 1 + nn
     // <= c - 64 <= 127 (the string is 0 past the sequence), its Z terms at half index h' <= c / 2
     // need t <= h' + 15 <= 111, so two blocks hold every term of an existing flip
