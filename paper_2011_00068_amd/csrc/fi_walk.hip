@@ -184,7 +184,7 @@ template <int SHAPE> struct FiWalkerOf<SHAPE, false> {
 template <int SHAPE> struct FiWalkerOf<SHAPE, true> {
     static constexpr bool big = SHAPE >= 5;
     using Lds = typename std::conditional<big, WaveLdsMfmaBig, WaveLdsMfma>::type;
-    using W = MfmaWalker<ShapeGK<SHAPE>::KW == 1 ? 2 : ShapeGK<SHAPE>::KW, big, Lds>;
+    using W = MfmaWalker<SHAPE == 0 ? 2 : MfmaKW<SHAPE>::value, big, Lds>;
     static constexpr int waves = big ? 5 : 8;
 };
 

@@ -142,7 +142,14 @@ struct MfmaFlip {
                          // the commits do not keep)
 };
 
-// KW: shift window words (c <= 32 KW); BIG: flips up to c = 191 (two tiles, four flips per
+// Window words of the matrix-core walker per shape: those of the bit-sliced walker, except that
+// shape 2 (c = 64, one length) takes the three-word walker, so that the two-word one serves
+// c <= 63 with a single K block.
+template <int SHAPE> struct MfmaKW {
+    static constexpr int value = SHAPE == 2 ? 3 : ShapeGK<SHAPE>::KW;
+};
+
+// KW: shift window words (c <= 32 KW; c <= 63 for KW = 2, see MfmaKW); BIG: flips up to c = 191 (two tiles, four flips per
 // lane: j = 2 l + g for g < 2 and j = 128 + 2 l + (g - 2) for g >= 2, i.e. half index l and
 // 64 + l); LdsT: the LDS layout (big whenever BIG, or in a mixed-length launch).
 template <int KW, bool BIG = false, class LdsT = WaveLdsMfma>
@@ -154,7 +161,7 @@ struct MfmaWalker {
     // (the string is 0 past the sequence; h >= nn), so t <= c; its Z term at 63 - h reads s^p at
     // 63 - 16 i - t >= 0, so t <= 63.  Every nonzero term has t <= the largest c of the walker
     // (127 with one tile, 191 with two).
-    static constexpr int kCMaxW = BIG ? (32 * KW < 191 ? 32 * KW : 191) : (32 * KW < 127 ? 32 * KW : 127);
+    static constexpr int kCMaxW = BIG ? (32 * KW < 191 ? 32 * KW : 191) : (KW == 1 ? 32 : KW == 2 ? 63 : KW == 3 ? 96 : 127);
     static constexpr int KB = (kCMaxW + 64) / 64;
     // K blocks of the second tile (BIG): its Y terms at half index 64 + h need t = kappa + 1 + nn
     // <= c - 64 <= 127 (the string is 0 past the sequence), its Z terms at half index h' <= c / 2

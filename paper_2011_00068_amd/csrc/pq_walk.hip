@@ -50,7 +50,7 @@ template <class Base> struct WaveLdsPqT : Base {
 template <int SHAPE> struct PqWalkerOf {
     static constexpr bool mfma = SHAPE >= 2 && SHAPE <= 4;
     using Lds = WaveLdsPqT<typename std::conditional<mfma, WaveLdsMfma, WaveLdsBits>::type>;
-    using type = typename std::conditional<mfma, MfmaWalker<ShapeGK<SHAPE>::KW, false, Lds>,
+    using type = typename std::conditional<mfma, MfmaWalker<MfmaKW<SHAPE>::value, false, Lds>,
                                            Walker<ShapeGK<SHAPE>::G, ShapeGK<SHAPE>::KW, false>>::type;
 };
 

@@ -24,13 +24,13 @@ __device__ __forceinline__ void run_any_mfma(WalkState *ws, uint64_t *tables, in
 {
     using Lds = typename MfmaShape<SHAPE>::Lds;
     if constexpr (SHAPE >= 0) {
-        run_walk<MfmaWalker<ShapeGK<SHAPE>::KW, MfmaShape<SHAPE>::big, Lds>, PW>(ws, tables, trace, scores, chunk,
+        run_walk<MfmaWalker<MfmaKW<SHAPE>::value, MfmaShape<SHAPE>::big, Lds>, PW>(ws, tables, trace, scores, chunk,
                                                                                   lds, zk);
     } else {
         switch (shape_for_length_dev(ws->L)) {
         case 0: run_walk<MfmaWalker<1, false, Lds>, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
-        case 1:
-        case 2: run_walk<MfmaWalker<2, false, Lds>, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
+        case 1: run_walk<MfmaWalker<2, false, Lds>, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
+        case 2: run_walk<MfmaWalker<3, false, Lds>, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
         case 3: run_walk<MfmaWalker<3, false, Lds>, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
         case 4: run_walk<MfmaWalker<4, false, Lds>, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
         case 5: run_walk<MfmaWalker<4, true, Lds>, PW>(ws, tables, trace, scores, chunk, lds, zk); break;
@@ -134,8 +134,8 @@ hipError_t launch_flip_scores_mfma(int L, int count, const uint32_t *x, int32_t 
     void (*k)(int, int, const uint32_t *, int32_t *) = nullptr;
     switch (shape_for_length(L)) {
     case 0: k = k_flip_scores_mfma<1, false>; break;
-    case 1:
-    case 2: k = k_flip_scores_mfma<2, false>; break;
+    case 1: k = k_flip_scores_mfma<2, false>; break;
+    case 2: k = k_flip_scores_mfma<3, false>; break;
     case 3: k = k_flip_scores_mfma<3, false>; break;
     case 4: k = k_flip_scores_mfma<4, false>; break;
     case 5: k = k_flip_scores_mfma<4, true>; break;
