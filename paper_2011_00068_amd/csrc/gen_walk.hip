@@ -65,6 +65,11 @@ struct GenMfmaWalker {
     static constexpr int kG = G;
     static constexpr int QR = 3; // shifts k = lane + 64 q + 1
     using Lds = WaveLdsGenMfma;
+    // K blocks of the first tile.  Its Y kinds (SF + off) read s at j + k <= L - 1, i.e. t <= L - 1,
+    // and its Z kinds (RV + 128, RV + 64) read s at j - k >= 0 with j <= 127 - 16 i, i.e. t <= 127:
+    // two blocks with one tile (L <= 128), three with two (L <= 192).  The second tile's Z kind
+    // (RV + 0, j <= 191) reaches t <= L + 14 and keeps KB.
+    static constexpr int KB1 = G <= 2 ? (KB < 2 ? KB : 2) : (KB < 3 ? KB : 3);
 
     int L, c, n;
     int lane;
@@ -210,30 +215,32 @@ struct GenMfmaWalker {
         lds_fence();
     }
 
+    template <int NKB>
     __device__ __forceinline__ mfma_v4i tile(uint32_t a_addr) const
     {
         const lds_cv4 *ap4 = (const lds_cv4 *)(uintptr_t)a_addr;
         const lds_cu32 *bp = (const lds_cu32 *)(uintptr_t)tb;
-        mfma_v4i a[KB], b[KB];
+        mfma_v4i a[NKB], b[NKB];
 #pragma unroll
-        for (int kb = 0; kb < KB; kb++) {
+        for (int kb = 0; kb < NKB; kb++) {
             a[kb] = ap4[4 * kb];
             b[kb] = mfma_v4i{(int)bp[16 * kb], (int)bp[16 * kb + 1], (int)bp[16 * kb + 2], (int)bp[16 * kb + 3]};
         }
         mfma_v4i acc = {0, 0, 0, 0};
 #pragma unroll
-        for (int kb = 0; kb < KB; kb++)
+        for (int kb = 0; kb < NKB; kb++)
             acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[kb], b[kb], acc, 0, 0, 0);
         return acc;
     }
 
+    template <int NKB>
     __device__ __forceinline__ mfma_v4i tile_all(uint32_t a_addr)
     {
-        mfma_v4i d = tile(a_addr);
+        mfma_v4i d = tile<NKB>(a_addr);
         if (planes > 8) {
             put_c(2);
             lds_fence();
-            const mfma_v4i hi = tile(a_addr);
+            const mfma_v4i hi = tile<NKB>(a_addr);
             d = d + hi * 64;
         }
         return d;
@@ -246,7 +253,7 @@ struct GenMfmaWalker {
 #pragma unroll
         for (int g = 0; g < G; g++)
             base[g] = mad24(Rv[g], 8, isl4);
-        const mfma_v4i d = tile_all(ta);
+        const mfma_v4i d = tile_all<KB1>(ta);
         // |G_j| <= 2 L^2: 24-bit products
         isl_j[0] = mad24(mult[0], d[0] + __builtin_amdgcn_ds_bpermute(bsrc, d[2]), base[0]);
         if constexpr (G >= 2)
@@ -254,7 +261,7 @@ struct GenMfmaWalker {
         if constexpr (G >= 3) {
             if (planes > 8) // the copies hold hi now: lo again for the second tile
                 put_c(1);
-            const mfma_v4i d2 = tile_all(ta2);
+            const mfma_v4i d2 = tile_all<KB>(ta2);
             isl_j[2] = mad24(mult[2], d2[0] + __builtin_amdgcn_ds_bpermute(bsrc, d2[1]), base[2]);
         }
     }
