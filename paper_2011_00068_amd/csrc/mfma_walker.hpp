@@ -528,12 +528,26 @@ struct MfmaWalker {
         }
     }
 
-    template <bool REG_X = true>
-    __device__ __forceinline__ void commit(int js, int32_t isl_new)
+    // What a commit of flip js reads, and the per-lane changes it derives from it.  The walker's
+    // state is not touched, so a walk can take this for its best candidate while that candidate's
+    // table probe is in flight, and apply it once the probe has confirmed the candidate.
+    struct CommitRead {
+        int32_t dq[QR];           // C'_kappa += f dq[q] (kappa = lane + 64 q)
+        int32_t d[BIG ? 2 : 1];   // rc' of half index 64 t + lane: += f0 d[t] (p = 0), f1 d[t] (p = 1)
+        int32_t f, f0, f1;        // uniform factors
+        int32_t sjs, emir, hjs, nps;
+        uint32_t sp_a, sq_a, sr_a;
+    };
+    // whether a walk takes commit_read for its best candidate during the probe: measured faster for
+    // c <= 63 (L = 101: 4.6 % per step), slower for the longer shapes, whose registers it crowds
+    static constexpr bool kSpecRead = KW <= 2 && !BIG;
+
+    __device__ __forceinline__ CommitRead commit_read(int js) const
     {
         // The index arithmetic of a commit is wave-uniform and runs on the scalar unit; the vector
         // instructions are the per-lane reads, selects and updates.
         const int lane = this->lane;
+        CommitRead r;
         // the lane that scores js and its slot (one tile: js < 128, slot = js & 1)
         const int ol = BIG ? (js & 127) >> 1 : js >> 1;
         const int slot = BIG ? (js >> 7) * 2 + (js & 1) : js & 1;
@@ -548,22 +562,26 @@ struct MfmaWalker {
             for (int g = 1; g < G; g++)
                 mj = slot == g ? __builtin_amdgcn_readlane(mult[g], ol) : mj;
         }
-        const int32_t f = mj >> 1;                   // -4 s_js (-2 s_c at the centre)
+        r.f = mj >> 1;                               // -4 s_js (-2 s_c at the centre)
         const int32_t sjs = ~((mj >> 31) << 1);      // s_js before the commit: -1 if mj > 0, else 1
         const int hjs = js >> 1;
         const int pis = js & 1;
         // (at the centre js = c these give kds = -1, no excluded shift, and nps = hjs)
         const int kds = c - 1 - js;                  // the excluded shift kappa_d of js
-        const int nps = c - ((js + 1) >> 1);         // half index of the mirror m' = 2c - js
-        // byte addresses of the strings of kind p, 2+p and (big) 4+p
         typedef __attribute__((address_space(3))) const int8_t lds_ci8;
-        typedef __attribute__((address_space(3))) int8_t lds_i8;
+        // byte addresses of the strings of kind p, 2+p and (big) 4+p
         const uint32_t s0 = (uint32_t)(uintptr_t)lds->str(0);
         const uint32_t sp_a = s0 + (uint32_t)pis * 4u * (uint32_t)(Lds::str_off(1) - Lds::str_off(0));
         const uint32_t sq_a = sp_a + 4u * (uint32_t)(Lds::str_off(2) - Lds::str_off(0));
         const uint32_t sr_a = BIG ? (uint32_t)(uintptr_t)lds->str(4) +
                                         (uint32_t)pis * 4u * (uint32_t)(Lds::str_off(5) - Lds::str_off(4))
                                   : 0u;
+        r.sjs = sjs;
+        r.hjs = hjs;
+        r.nps = c - ((js + 1) >> 1);                 // half index of the mirror m' = 2c - js
+        r.sp_a = sp_a;
+        r.sq_a = sq_a;
+        r.sr_a = sr_a;
         // dC'_kappa = -4 s_js (p_kappa + q_kappa), p without the excluded shift kappa_d, read from
         // the +-1 byte strings (0 past either end, so lanes with kappa >= c add nothing): p from
         // s^p at hjs + 1 + kappa, q = s^p_{hjs-1-kappa} from the reversed string (s^p_{63-u}, or
@@ -581,7 +599,7 @@ struct MfmaWalker {
         }
 #pragma unroll
         for (int q = 0; q < QR; q++)
-            Cv[q] = mad24_u(drop_where(lane + 64 * q == kds, pv[q]) + qv[q], f, Cv[q]);
+            r.dq[q] = drop_where(lane + 64 * q == kds, pv[q]) + qv[q];
         // rc'_j of the owned flips of js's parity (see the file header).  Partner 2 j - js is s^p at
         // half index u1 = 2h - hjs >= -63 (-95 big), read from the kind-p string, whose zero pad
         // covers the negative ones; partner 2 j - m' is s^p at u2 = 2h + hjs + p - c, read as byte
@@ -591,22 +609,36 @@ struct MfmaWalker {
         // where it is the excluded shift of j (js = 3 j - 2c, i.e. 3 h = hjs + c - p), and flip js
         // itself does not change.  s_m' = (-1)^(c - js) s_js (also at the centre, where m' = js).
         const int32_t emir = 1 - 2 * ((c ^ js) & 1);
-        {
-            const int32_t eps = js == c ? 0 : emir;
-            const int32_t f1 = pis ? sjs : 0, f0 = sjs - f1;
-            const int tri = hjs + c - pis;
-            lds_ci8 *const a1 = (lds_ci8 *)(uintptr_t)su(sp_a - (uint32_t)hjs) + 2 * lane;
-            lds_ci8 *const a2 =
-                (lds_ci8 *)(uintptr_t)su((BIG ? sr_a : sq_a) + (uint32_t)((BIG ? 127 : 63) - hjs - pis + c)) - 2 * lane;
+        r.emir = emir;
+        const int32_t eps = js == c ? 0 : emir;
+        r.f1 = pis ? sjs : 0;
+        r.f0 = sjs - r.f1;
+        const int tri = hjs + c - pis;
+        lds_ci8 *const a1 = (lds_ci8 *)(uintptr_t)su(sp_a - (uint32_t)hjs) + 2 * lane;
+        lds_ci8 *const a2 =
+            (lds_ci8 *)(uintptr_t)su((BIG ? sr_a : sq_a) + (uint32_t)((BIG ? 127 : 63) - hjs - pis + c)) - 2 * lane;
 #pragma unroll
-            for (int t = 0; t < (BIG ? 2 : 1); t++) {
-                const int32_t h = 64 * t + lane;
-                const int32_t v1 = a1[128 * t];
-                const int32_t v2 = a2[-128 * t];
-                const int32_t d = drop_where(h == hjs, mad24_u(v2, eps, drop_where(3 * h == tri, v1)));
-                rc[2 * t] = mad24_u(d, f0, rc[2 * t]);
-                rc[2 * t + 1] = mad24_u(d, f1, rc[2 * t + 1]);
-            }
+        for (int t = 0; t < (BIG ? 2 : 1); t++) {
+            const int32_t h = 64 * t + lane;
+            const int32_t v1 = a1[128 * t];
+            const int32_t v2 = a2[-128 * t];
+            r.d[t] = drop_where(h == hjs, mad24_u(v2, eps, drop_where(3 * h == tri, v1)));
+        }
+        return r;
+    }
+
+    // Commit flip js with what commit_read(js) returned (nothing written since).
+    template <bool REG_X = true>
+    __device__ __forceinline__ void commit_apply(int js, int32_t isl_new, const CommitRead &r)
+    {
+        typedef __attribute__((address_space(3))) int8_t lds_i8;
+#pragma unroll
+        for (int q = 0; q < QR; q++)
+            Cv[q] = mad24_u(r.dq[q], r.f, Cv[q]);
+#pragma unroll
+        for (int t = 0; t < (BIG ? 2 : 1); t++) {
+            rc[2 * t] = mad24_u(r.d[t], r.f0, rc[2 * t]);
+            rc[2 * t + 1] = mad24_u(r.d[t], r.f1, rc[2 * t + 1]);
         }
         // the flipped symbol (lane 0) and its mirror m' = 2c - js (lane 1; the centre again when js
         // = c) in the +-1 byte strings: kind p at byte a, kind 2+p at byte 63 - a (when a <= 63; a
@@ -616,9 +648,12 @@ struct MfmaWalker {
         // writes: lanes 2..63 repeat lane 1's byte (the same address and value), which costs no
         // exec mask around the writes.
         {
+            const uint32_t sp_a = r.sp_a, sq_a = r.sq_a, sr_a = r.sr_a;
+            (void)sq_a;
+            (void)sr_a;
             // (per-lane values by v_writelane: lane 0's replaces the others', no compare and select)
-            const int a = write_lane<0>(nps, hjs);
-            const int32_t v = write_lane<0>(-emir * sjs, -sjs);
+            const int a = write_lane<0>(r.nps, r.hjs);
+            const int32_t v = write_lane<0>(-r.emir * r.sjs, -r.sjs);
             *(lds_i8 *)(uintptr_t)(sp_a + (uint32_t)a) = (int8_t)v;
             if constexpr (BIG) {
                 *(lds_i8 *)(uintptr_t)(sr_a + 127u - (uint32_t)a) = (int8_t)v; // a <= 95
@@ -642,6 +677,127 @@ struct MfmaWalker {
             h ^= ((uint64_t)uniform((uint32_t)(z >> 32)) << 32) | uniform((uint32_t)z);
         }
         isl = isl_new;
+    }
+
+    template <bool REG_X = true>
+    __device__ __forceinline__ void commit(int js, int32_t isl_new)
+    {
+        if constexpr (kSpecRead) {
+            commit_apply<REG_X>(js, isl_new, commit_read(js));
+        } else {
+            // the same steps in one piece (the split form measured slower for these shapes)
+            // The index arithmetic of a commit is wave-uniform and runs on the scalar unit; the vector
+            // instructions are the per-lane reads, selects and updates.
+            const int lane = this->lane;
+            // the lane that scores js and its slot (one tile: js < 128, slot = js & 1)
+            const int ol = BIG ? (js & 127) >> 1 : js >> 1;
+            const int slot = BIG ? (js >> 7) * 2 + (js & 1) : js & 1;
+            // mult of js at its owner lane: -8 s_js, or -4 s_c at the centre
+            int32_t mj = __builtin_amdgcn_readlane(mult[0], ol);
+            if constexpr (G == 2) {
+                // both slots' values, then one scalar select (left to itself the compiler branches)
+                const int32_t m1 = __builtin_amdgcn_readlane(mult[1], ol);
+                asm("s_cmp_eq_u32 %1, 0\n\ts_cselect_b32 %0, %2, %3" : "=s"(mj) : "s"(slot), "s"(mj), "s"(m1) : "scc");
+            } else {
+#pragma unroll
+                for (int g = 1; g < G; g++)
+                    mj = slot == g ? __builtin_amdgcn_readlane(mult[g], ol) : mj;
+            }
+            const int32_t f = mj >> 1;                   // -4 s_js (-2 s_c at the centre)
+            const int32_t sjs = ~((mj >> 31) << 1);      // s_js before the commit: -1 if mj > 0, else 1
+            const int hjs = js >> 1;
+            const int pis = js & 1;
+            // (at the centre js = c these give kds = -1, no excluded shift, and nps = hjs)
+            const int kds = c - 1 - js;                  // the excluded shift kappa_d of js
+            const int nps = c - ((js + 1) >> 1);         // half index of the mirror m' = 2c - js
+            // byte addresses of the strings of kind p, 2+p and (big) 4+p
+            typedef __attribute__((address_space(3))) const int8_t lds_ci8;
+            typedef __attribute__((address_space(3))) int8_t lds_i8;
+            const uint32_t s0 = (uint32_t)(uintptr_t)lds->str(0);
+            const uint32_t sp_a = s0 + (uint32_t)pis * 4u * (uint32_t)(Lds::str_off(1) - Lds::str_off(0));
+            const uint32_t sq_a = sp_a + 4u * (uint32_t)(Lds::str_off(2) - Lds::str_off(0));
+            const uint32_t sr_a = BIG ? (uint32_t)(uintptr_t)lds->str(4) +
+                                            (uint32_t)pis * 4u * (uint32_t)(Lds::str_off(5) - Lds::str_off(4))
+                                      : 0u;
+            // dC'_kappa = -4 s_js (p_kappa + q_kappa), p without the excluded shift kappa_d, read from
+            // the +-1 byte strings (0 past either end, so lanes with kappa >= c add nothing): p from
+            // s^p at hjs + 1 + kappa, q = s^p_{hjs-1-kappa} from the reversed string (s^p_{63-u}, or
+            // s^p_{127-u} when half indices reach past 64); at the centre p = q and u = q, so the
+            // factor is halved instead
+            // (the uniform bases go through readfirstlane, a no-op on a scalar, so that the per-lane
+            // offsets stay one add and the constant ones fold into the reads' offset fields)
+            lds_ci8 *const pl = (lds_ci8 *)(uintptr_t)su(sp_a + (uint32_t)(hjs + 1)) + lane;
+            lds_ci8 *const ql = (lds_ci8 *)(uintptr_t)su((BIG ? sr_a + 128u : sq_a + 64u) - (uint32_t)hjs) + lane;
+            int32_t pv[QR], qv[QR];
+#pragma unroll
+            for (int q = 0; q < QR; q++) {
+                pv[q] = pl[64 * q];
+                qv[q] = ql[64 * q];
+            }
+#pragma unroll
+            for (int q = 0; q < QR; q++)
+                Cv[q] = mad24_u(drop_where(lane + 64 * q == kds, pv[q]) + qv[q], f, Cv[q]);
+            // rc'_j of the owned flips of js's parity (see the file header).  Partner 2 j - js is s^p at
+            // half index u1 = 2h - hjs >= -63 (-95 big), read from the kind-p string, whose zero pad
+            // covers the negative ones; partner 2 j - m' is s^p at u2 = 2h + hjs + p - c, read as byte
+            // 63 - u2 of the kind-2+p string (127 - u2 of the kind-4+p string when BIG), which holds 0
+            // past the sequence's start; u2 < 64 (< 128) for every flip j < c.  Flips j >= c read
+            // anything and keep it (their rc' is not used).  The term of partner 2 j - js is dropped
+            // where it is the excluded shift of j (js = 3 j - 2c, i.e. 3 h = hjs + c - p), and flip js
+            // itself does not change.  s_m' = (-1)^(c - js) s_js (also at the centre, where m' = js).
+            const int32_t emir = 1 - 2 * ((c ^ js) & 1);
+            {
+                const int32_t eps = js == c ? 0 : emir;
+                const int32_t f1 = pis ? sjs : 0, f0 = sjs - f1;
+                const int tri = hjs + c - pis;
+                lds_ci8 *const a1 = (lds_ci8 *)(uintptr_t)su(sp_a - (uint32_t)hjs) + 2 * lane;
+                lds_ci8 *const a2 =
+                    (lds_ci8 *)(uintptr_t)su((BIG ? sr_a : sq_a) + (uint32_t)((BIG ? 127 : 63) - hjs - pis + c)) - 2 * lane;
+#pragma unroll
+                for (int t = 0; t < (BIG ? 2 : 1); t++) {
+                    const int32_t h = 64 * t + lane;
+                    const int32_t v1 = a1[128 * t];
+                    const int32_t v2 = a2[-128 * t];
+                    const int32_t d = drop_where(h == hjs, mad24_u(v2, eps, drop_where(3 * h == tri, v1)));
+                    rc[2 * t] = mad24_u(d, f0, rc[2 * t]);
+                    rc[2 * t + 1] = mad24_u(d, f1, rc[2 * t + 1]);
+                }
+            }
+            // the flipped symbol (lane 0) and its mirror m' = 2c - js (lane 1; the centre again when js
+            // = c) in the +-1 byte strings: kind p at byte a, kind 2+p at byte 63 - a (when a <= 63; a
+            // dummy word otherwise), kind 4+p at byte 127 - a, each written with its new value; the
+            // parity bit strings are rebuilt at the next (re)start.  No byte read above is written here
+            // (the one at the mirror is the excluded shift, whose value is not used).  Every lane
+            // writes: lanes 2..63 repeat lane 1's byte (the same address and value), which costs no
+            // exec mask around the writes.
+            {
+                // (per-lane values by v_writelane: lane 0's replaces the others', no compare and select)
+                const int a = write_lane<0>(nps, hjs);
+                const int32_t v = write_lane<0>(-emir * sjs, -sjs);
+                *(lds_i8 *)(uintptr_t)(sp_a + (uint32_t)a) = (int8_t)v;
+                if constexpr (BIG) {
+                    *(lds_i8 *)(uintptr_t)(sr_a + 127u - (uint32_t)a) = (int8_t)v; // a <= 95
+                    const uint32_t qa = a <= 63 ? sq_a + 63u - (uint32_t)a
+                                                : (uint32_t)(uintptr_t)reinterpret_cast<int8_t *>(&lds->book[7]);
+                    *(lds_i8 *)(uintptr_t)qa = (int8_t)v;
+                } else {
+                    *(lds_i8 *)(uintptr_t)(sq_a + 63u - (uint32_t)a) = (int8_t)v; // a <= 63
+                }
+                // (the free bits in lds->xw are not kept: sync_x_lds() reads them off the strings)
+            }
+            lds_fence();
+#pragma unroll
+            for (int g = 0; g < G; g++)
+                mult[g] = negate_where(flip(g) == js, mult[g]);
+            if (REG_X)
+                xflip_uniform(x, js);
+            x0 ^= js < 32 ? 1u << js : 0u;
+            if (REG_X) { // else the caller sets h (it has the neighbour's hash from its probe)
+                const uint64_t z = zk[js];
+                h ^= ((uint64_t)uniform((uint32_t)(z >> 32)) << 32) | uniform((uint32_t)z);
+            }
+            isl = isl_new;
+        }
     }
 };
 

@@ -33,6 +33,8 @@
 
 #pragma once
 
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace liblabs {
@@ -58,6 +60,18 @@ struct WaveLdsBits {
 // from it)
 using WaveLdsDirect = WaveLdsBits;
 template <bool DIRECT> struct LdsOf { using type = WaveLdsBits; };
+
+// A walker's commit split into a read part and an apply part (CommitRead, see the matrix-core
+// walker), or none.
+struct NoCommitRead {};
+template <class W, class = void> struct CommitReadOf {
+    using type = NoCommitRead;
+    static constexpr bool value = false;
+};
+template <class W> struct CommitReadOf<W, std::void_t<typename W::CommitRead>> {
+    using type = typename W::CommitRead;
+    static constexpr bool value = W::kSpecRead;
+};
 
 __device__ inline void lds_fence() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront"); __builtin_amdgcn_wave_barrier(); }
 
@@ -804,6 +818,9 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
             uint64_t h_new = 0; // hash of the chosen neighbour (from its probe)
             static_assert(PW >= 1 && PW <= 2, "one or two candidates per probe round");
             uint32_t cand[PW];
+            // the commit's reads for the best candidate, taken while its probe is in flight
+            [[maybe_unused]] typename CommitReadOf<W>::type pre;
+            int js_pre = -1;
             // One round: the PW best keys, probed together; true when it settles the step (a move
             // found, or no candidate left).
             auto probe_round = [&]() -> bool {
@@ -835,6 +852,10 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
                 // every lane loads (lanes from PW on repeat lane 0's probe, an empty candidate reads
                 // the slot of flip n - 1: all addresses are valid); only the candidates' lanes count
                 const uint64_t got = T[slot_of(hc, x0, exact, tlog2)];
+                if constexpr (CommitReadOf<W>::value) {
+                    js_pre = (int)(cand[0] & 255u);
+                    pre = w.commit_read(js_pre);
+                }
                 uint64_t pmask = 0;
 #pragma unroll
                 for (int i = 0; i < PW; i++)
@@ -876,7 +897,14 @@ __device__ __forceinline__ void run_walk_impl(WalkState *__restrict__ wsp, uint6
             trapped = (int32_t)((uint32_t)js >> 31);
             lim_in = js < 0 ? ts : lim_in;
             js = max(js, 0);
-            w.template commit<false>(js, isl_new);
+            if constexpr (CommitReadOf<W>::value) {
+                if (js == js_pre)
+                    w.template commit_apply<false>(js, isl_new, pre);
+                else
+                    w.template commit<false>(js, isl_new);
+            } else {
+                w.template commit<false>(js, isl_new);
+            }
             w.h = h_new;
             {
                 const uint32_t s_new = (uint32_t)slot_of(w.h, w.x0, exact, tlog2);
