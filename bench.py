@@ -131,9 +131,17 @@ def cpu_baseline(budget_s=10.0):
             res += list(ex.map(one, range(len(res), min(WALKS, len(res) + threads))))
     dt = time.perf_counter() - t0
     flips = sum(r["flip_evals"] for r in res)
+    # the same on one thread, on the walks that follow (about a quarter of the budget)
+    one_flips, one_walks = 0, 0
+    t1 = time.perf_counter()
+    while time.perf_counter() - t1 < budget_s / 4 and len(res) + one_walks < WALKS:
+        one_flips += one(len(res) + one_walks)["flip_evals"]
+        one_walks += 1
+    dt1 = time.perf_counter() - t1
     return {"value": flips / dt, "unit": "flip-evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(res)} of the {WALKS} walks, all {STEPS} steps each, L={L}, "
-                      f"{threads} threads; {dt:.1f} s wall"}, res
+                      f"{threads} threads; {dt:.1f} s wall",
+            "one_thread": {"value": one_flips / dt1 if dt1 > 0 else None, "walks": one_walks}}, res
 
 
 def plain_form(labs, walks=32):
