@@ -165,7 +165,7 @@ def plain_form(labs, walks=32):
             "time_to_F5": time_to_target(res, per_walk_ms, STEPS), "time_to_F8": time_to_f8(res)}, res
 
 
-def serving(labs, rate=20.0, n_requests=100, seed=SEED, target_F=(8, 1)):
+def serving(labs, rate=20.0, n_requests=100, seed=SEED, target_F=(8, 1), steps_per_tick=256):
     """The serving workload: Poisson arrivals (seeded), each request one odd L uniform in
     [201, 303] with 256 walks, 10^8 flip evaluations and stop threshold target_F (F >= 8), admitted
     by device memory for walk state.  Returns latency percentiles (submission to completion: the
@@ -176,7 +176,7 @@ def serving(labs, rate=20.0, n_requests=100, seed=SEED, target_F=(8, 1)):
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate, size=n_requests)
     lengths = rng.choice(np.arange(201, 304, 2), size=n_requests)
-    srv = labs.Server(device_mem_bytes=8 << 30, table_log2=TABLE_LOG2, steps_per_tick=256)
+    srv = labs.Server(device_mem_bytes=8 << 30, table_log2=TABLE_LOG2, steps_per_tick=steps_per_tick)
     t0 = time.perf_counter()
     jobs = []
     next_t = 0.0
