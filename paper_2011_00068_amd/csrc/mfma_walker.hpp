@@ -85,6 +85,12 @@ struct alignas(16) WaveLdsMfmaT {
     static_assert(NSTR == 4 ? (80 >= SEQ_DWORDS) : (144 >= SEQ_DWORDS && 112 >= SEQ_DWORDS &&
                                                     576 >= 3 * 144 + SEQ_DWORDS),
                   "strings overlap");
+    // A commit writes the mirror's byte of a kind-4+p string at 127 - a for its half index
+    // a <= c <= 191: half indices above 127, which that string does not hold, land up to 64 bytes
+    // before it, in the gap after the previous string, which nothing reads
+    static_assert(NSTR == 4 || (4 * (str_off(4) - str_off(3) - SEQ_DWORDS) >= 64 &&
+                                4 * (str_off(5) - str_off(4) - SEQ_DWORDS) >= 64),
+                  "64 free bytes before each kind-4+p string");
     // zero bytes before the kind-p strings (string 0: the leading pad; string 1: the gap)
     static_assert(4 * str_off(0) >= (NSTR == 4 ? 63 : 95) &&
                       4 * (str_off(1) - str_off(0) - SEQ_DWORDS) >= (NSTR == 4 ? 63 : 95),
@@ -656,7 +662,7 @@ struct MfmaWalker {
             const int32_t v = write_lane<0>(-r.emir * r.sjs, -r.sjs);
             *(lds_i8 *)(uintptr_t)(sp_a + (uint32_t)a) = (int8_t)v;
             if constexpr (BIG) {
-                *(lds_i8 *)(uintptr_t)(sr_a + 127u - (uint32_t)a) = (int8_t)v; // a <= 95
+                *(lds_i8 *)(uintptr_t)(sr_a + 127u - (uint32_t)a) = (int8_t)v; // (a <= c: beyond 127 into the gap)
                 const uint32_t qa = a <= 63 ? sq_a + 63u - (uint32_t)a
                                             : (uint32_t)(uintptr_t)reinterpret_cast<int8_t *>(&lds->book[7]);
                 *(lds_i8 *)(uintptr_t)qa = (int8_t)v;
@@ -776,7 +782,7 @@ struct MfmaWalker {
                 const int32_t v = write_lane<0>(-emir * sjs, -sjs);
                 *(lds_i8 *)(uintptr_t)(sp_a + (uint32_t)a) = (int8_t)v;
                 if constexpr (BIG) {
-                    *(lds_i8 *)(uintptr_t)(sr_a + 127u - (uint32_t)a) = (int8_t)v; // a <= 95
+                    *(lds_i8 *)(uintptr_t)(sr_a + 127u - (uint32_t)a) = (int8_t)v; // (a <= c: beyond 127 into the gap)
                     const uint32_t qa = a <= 63 ? sq_a + 63u - (uint32_t)a
                                                 : (uint32_t)(uintptr_t)reinterpret_cast<int8_t *>(&lds->book[7]);
                     *(lds_i8 *)(uintptr_t)qa = (int8_t)v;
