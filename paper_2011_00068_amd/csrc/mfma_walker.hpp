@@ -85,12 +85,16 @@ struct alignas(16) WaveLdsMfmaT {
     static_assert(NSTR == 4 ? (80 >= SEQ_DWORDS) : (144 >= SEQ_DWORDS && 112 >= SEQ_DWORDS &&
                                                     576 >= 3 * 144 + SEQ_DWORDS),
                   "strings overlap");
-    // A commit writes the mirror's byte of a kind-4+p string at 127 - a for its half index
-    // a <= c <= 191: half indices above 127, which that string does not hold, land up to 64 bytes
-    // before it, in the gap after the previous string, which nothing reads
-    static_assert(NSTR == 4 || (4 * (str_off(4) - str_off(3) - SEQ_DWORDS) >= 64 &&
-                                4 * (str_off(5) - str_off(4) - SEQ_DWORDS) >= 64),
-                  "64 free bytes before each kind-4+p string");
+    // A commit writes the mirror's byte of a kind-2+p string (one-tile walker, in either layout)
+    // or kind-4+p string (two tiles) at 63 - a / 127 - a for its half index a <= c (127 / 191):
+    // half indices the string does not hold land up to 64 bytes before it, in the gap after the
+    // previous string, which nothing reads (the two-tile walker's kind-2+p write goes to a dummy
+    // word instead)
+    static_assert(4 * (str_off(2) - str_off(1) - SEQ_DWORDS) >= 64 &&
+                      4 * (str_off(3) - str_off(2) - SEQ_DWORDS) >= 64 &&
+                      (NSTR == 4 || (4 * (str_off(4) - str_off(3) - SEQ_DWORDS) >= 64 &&
+                                     4 * (str_off(5) - str_off(4) - SEQ_DWORDS) >= 64)),
+                  "64 free bytes before each string a mirror byte can miss");
     // zero bytes before the kind-p strings (string 0: the leading pad; string 1: the gap)
     static_assert(4 * str_off(0) >= (NSTR == 4 ? 63 : 95) &&
                       4 * (str_off(1) - str_off(0) - SEQ_DWORDS) >= (NSTR == 4 ? 63 : 95),
@@ -667,7 +671,7 @@ struct MfmaWalker {
                                             : (uint32_t)(uintptr_t)reinterpret_cast<int8_t *>(&lds->book[7]);
                 *(lds_i8 *)(uintptr_t)qa = (int8_t)v;
             } else {
-                *(lds_i8 *)(uintptr_t)(sq_a + 63u - (uint32_t)a) = (int8_t)v; // a <= 63
+                *(lds_i8 *)(uintptr_t)(sq_a + 63u - (uint32_t)a) = (int8_t)v; // (a <= c: beyond 63 into the gap)
             }
             // (the free bits in lds->xw are not kept: sync_x_lds() reads them off the strings)
         }
@@ -787,7 +791,7 @@ struct MfmaWalker {
                                                 : (uint32_t)(uintptr_t)reinterpret_cast<int8_t *>(&lds->book[7]);
                     *(lds_i8 *)(uintptr_t)qa = (int8_t)v;
                 } else {
-                    *(lds_i8 *)(uintptr_t)(sq_a + 63u - (uint32_t)a) = (int8_t)v; // a <= 63
+                    *(lds_i8 *)(uintptr_t)(sq_a + 63u - (uint32_t)a) = (int8_t)v; // (a <= c: beyond 63 into the gap)
                 }
                 // (the free bits in lds->xw are not kept: sync_x_lds() reads them off the strings)
             }
