@@ -81,6 +81,23 @@ def test_plan_reruns_reuse_tables(labs, variant):
     plan.close()
 
 
+def test_chunked_plan_reruns_reuse_tables(labs):
+    # The same with the walks cut into launches of 37 steps (each launch resumes a walk from its
+    # state record, epoch included) and the pulling persistent grid: three runs, each equal to
+    # the oracle.
+    cfgs = [labs.make_cfg(255, SEED, 0, steps=300, table_log2=2, restart_period=29, trace=True),
+            labs.make_cfg(7, SEED, 7, steps=200, table_log2=4, trace=True),
+            labs.make_cfg(101, SEED, 4, steps=300, table_log2=3, restart_period=50, trace=True),
+            labs.make_cfg(303, SEED, 2, steps=250, table_log2=3, restart_period=41, trace=True)]
+    refs = [oracle_walk(c, trace=True) for c in cfgs]
+    plan = labs.WalkPlan(cfgs, steps_per_launch=37, persistent=2)
+    for run in range(3):
+        plan.run()
+        for i, (g, r) in enumerate(zip(plan.results(), refs)):
+            assert_same(g, r, f"run {run}, L = {cfgs[i].L}")
+    plan.close()
+
+
 @pytest.mark.parametrize("L", [3, 5, 7, 9, 13, 33, 63, 65, 95, 97, 101, 127, 129, 131, 191, 193, 201,
                                255, 257, 259, 303, 321, 383])
 def test_short_walks_every_shape(labs, L):
