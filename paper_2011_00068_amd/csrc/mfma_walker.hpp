@@ -588,7 +588,7 @@ struct MfmaWalker {
                                   : 0u;
         r.sjs = sjs;
         r.hjs = hjs;
-        r.nps = c - ((js + 1) >> 1);                 // half index of the mirror m' = 2c - js
+        r.nps = c - hjs - pis;                       // half index of the mirror m' = 2c - js
         r.sp_a = sp_a;
         r.sq_a = sq_a;
         r.sr_a = sr_a;
@@ -618,7 +618,7 @@ struct MfmaWalker {
         // anything and keep it (their rc' is not used).  The term of partner 2 j - js is dropped
         // where it is the excluded shift of j (js = 3 j - 2c, i.e. 3 h = hjs + c - p), and flip js
         // itself does not change.  s_m' = (-1)^(c - js) s_js (also at the centre, where m' = js).
-        const int32_t emir = 1 - 2 * ((c ^ js) & 1);
+        const int32_t emir = pis ? -(eps8[0] >> 3) : (eps8[0] >> 3); // (-1)^(c - js)
         r.emir = emir;
         const int32_t eps = js == c ? 0 : emir;
         r.f1 = pis ? sjs : 0;
@@ -719,7 +719,7 @@ struct MfmaWalker {
             const int pis = js & 1;
             // (at the centre js = c these give kds = -1, no excluded shift, and nps = hjs)
             const int kds = c - 1 - js;                  // the excluded shift kappa_d of js
-            const int nps = c - ((js + 1) >> 1);         // half index of the mirror m' = 2c - js
+            const int nps = c - hjs - pis;               // half index of the mirror m' = 2c - js
             // byte addresses of the strings of kind p, 2+p and (big) 4+p
             typedef __attribute__((address_space(3))) const int8_t lds_ci8;
             typedef __attribute__((address_space(3))) int8_t lds_i8;
@@ -755,7 +755,7 @@ struct MfmaWalker {
             // anything and keep it (their rc' is not used).  The term of partner 2 j - js is dropped
             // where it is the excluded shift of j (js = 3 j - 2c, i.e. 3 h = hjs + c - p), and flip js
             // itself does not change.  s_m' = (-1)^(c - js) s_js (also at the centre, where m' = js).
-            const int32_t emir = 1 - 2 * ((c ^ js) & 1);
+            const int32_t emir = pis ? -(eps8[0] >> 3) : (eps8[0] >> 3); // (-1)^(c - js)
             {
                 const int32_t eps = js == c ? 0 : emir;
                 const int32_t f1 = pis ? sjs : 0, f0 = sjs - f1;
