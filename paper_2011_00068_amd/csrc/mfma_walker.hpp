@@ -1,5 +1,5 @@
 // mfma_walker.hpp -- the skew walker with its flip scoring on the matrix cores (gfx950
-// v_mfma_i32_16x16x64_i8), for L <= 255 (c <= 127).
+// v_mfma_i32_16x16x64_i8): one tile for L <= 255 (c <= 127), two up to L = 383 (c <= 191).
 //
 // Scoring (derived from Eq. (1) and (4), as in the bit-sliced walker): for flip j = 2h + p
 // (parity p = j & 1, h = j >> 1, mirror m = L-1-j, d = m - j = 2 (c - j), kappa_d = c-1-j)
@@ -159,9 +159,10 @@ template <int SHAPE> struct MfmaKW {
     static constexpr int value = SHAPE == 2 ? 3 : ShapeGK<SHAPE>::KW;
 };
 
-// KW: shift window words (c <= 32 KW; c <= 63 for KW = 2, see MfmaKW); BIG: flips up to c = 191 (two tiles, four flips per
-// lane: j = 2 l + g for g < 2 and j = 128 + 2 l + (g - 2) for g >= 2, i.e. half index l and
-// 64 + l); LdsT: the LDS layout (big whenever BIG, or in a mixed-length launch).
+// KW: shift window words (c <= 32 KW; c <= 63 for KW = 2, see MfmaKW); BIG: flips up to
+// c = 191 (two tiles, four flips per lane: j = 2 l + g for g < 2 and j = 128 + 2 l + (g - 2)
+// for g >= 2, i.e. half index l and 64 + l); LdsT: the LDS layout (big whenever BIG, or in a
+// mixed-length launch).
 template <int KW, bool BIG = false, class LdsT = WaveLdsMfma>
 struct MfmaWalker {
     static constexpr int G = BIG ? 4 : 2;

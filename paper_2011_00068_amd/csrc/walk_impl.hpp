@@ -1,4 +1,4 @@
-// walk_kernels.hip -- the gfx950 kernels of the skew-symmetric self-avoiding walk
+// walk_impl.hpp -- the gfx950 kernels of the skew-symmetric self-avoiding walk
 // (Section 3, Algorithm 1 of Brest & Boskovic, arXiv:2011.00068, in its self-avoiding-walk
 // reading) and of the batched one-flip evaluation.
 //
