@@ -1,7 +1,7 @@
-// enum_kernels.hip -- the exhaustive minimum over the skew-symmetric space of one odd length (Eq. (2), (4); Section 1's
-// search-space reduction), grouped by the two ISL-preserving symmetries of skew sequences:
-// negation (x -> x ^ A, A = the n free bits) and alternation s_i -> (-1)^i s_i (x -> x ^ O, O =
-// the free bits at odd positions).  Every free-bit vector lies in exactly one group
+// enum_kernels.hip -- the exhaustive minimum over the skew-symmetric space of one odd length
+// (Eq. (2), (4); Section 1's search-space reduction), grouped by the two ISL-preserving
+// symmetries of skew sequences: negation (x -> x ^ A, A = the n free bits) and alternation
+// s_i -> (-1)^i s_i (x -> x ^ O, O = the free bits at odd positions).  Every free-bit vector lies in exactly one group
 // {x, x^A, x^O, x^A^O} with x = r << 2, so the kernel scores one member per group (a quarter of
 // the 2^n sequences) and counts four.
 //
