@@ -27,7 +27,8 @@
  *     others are synchronous.
  *   - Every computation of the search runs in the library's gfx950 kernels; there is no CPU
  *     fallback.  A missing or unusable GPU returns LABS_EDEVICE.  (labs_isl_threshold, which only
- *     converts a stop parameter, is host integer arithmetic.)
+ *     converts a stop parameter, and labs_from_hex / labs_to_hex, which convert sequence notation,
+ *     are host code.)
  */
 #ifndef LABS_H
 #define LABS_H
@@ -85,6 +86,19 @@ int labs_merit(int32_t L, const int8_t *s, double *F_out);
  * (a conversion of a stop parameter; no device work).  1 <= L <= 65535, num > 0, den > 0, else
  * LABS_EINVAL; a bound above INT64_MAX is clamped to it.  isl_out: host. */
 int labs_isl_threshold(int32_t L, int64_t num, int64_t den, int64_t *isl_out);
+
+/* Table 1's sequence notation (Section 4): each hex digit gives 4 bits, most significant first;
+ * leading 0 bits are dropped down to L symbols; bit 0 is +1 and bit 1 is -1.  Host code only (a
+ * conversion of inputs and outputs, no device work).
+ *   labs_from_hex: hex is a NUL-terminated string of 0-9, a-f, A-F with at least L bits; every
+ *     dropped bit must be 0.  s_out: host, L int8 symbols, written only on success.  LABS_EINVAL for
+ *     another character, too few bits, a dropped bit 1, L outside [1, 65535] or a NULL pointer.
+ *   labs_to_hex: the shortest form, ceil(L/4) upper-case digits (the first digit holds the
+ *     4 ceil(L/4) - L zero pad bits), then a NUL.  out: host, cap bytes, at least ceil(L/4) + 1.
+ *     LABS_EINVAL for a symbol other than +1 / -1, a short cap, L outside [1, 65535] or a NULL
+ *     pointer (out's contents are then unspecified). */
+int labs_from_hex(const char *hex, int32_t L, int8_t *s_out);
+int labs_to_hex(int32_t L, const int8_t *s, char *out, int32_t cap);
 
 /* Batched Eq. (1)-(3) and the PSL of Section 1 (max_{k>=1} |C_k|) for `count` sequences of
  * length L stored back to back (row r at s_dev + r*L).  Device buffers: s_dev (count*L int8),

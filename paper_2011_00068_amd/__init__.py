@@ -42,7 +42,7 @@ JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_CANCELLED = 0, 1, 2, 3
 # Every symbol include/labs.h declares (checked by the tests).
 EXPORTS = [
     "labs_strerror", "labs_last_error", "labs_device_info", "labs_probe_lds_read",
-    "labs_isl", "labs_merit", "labs_isl_threshold", "labs_isl_batch_dev", "labs_enum_skew_dev", "labs_enum_skew_min",
+    "labs_isl", "labs_merit", "labs_isl_threshold", "labs_from_hex", "labs_to_hex", "labs_isl_batch_dev", "labs_enum_skew_dev", "labs_enum_skew_min",
     "labs_enum_skew_min_noalloc",
     "labs_flip_scores_dev",
     "labs_walk_batch", "labs_walk_plan_create", "labs_walk_plan_run", "labs_walk_plan_results",
@@ -192,6 +192,8 @@ def lib():
     L.labs_isl.argtypes = [i32, vp, P(i64)]
     L.labs_merit.argtypes = [i32, vp, P(ctypes.c_double)]
     L.labs_isl_threshold.argtypes = [i32, i64, i64, P(i64)]
+    L.labs_from_hex.argtypes = [ctypes.c_char_p, i32, vp]
+    L.labs_to_hex.argtypes = [i32, vp, ctypes.c_char_p, i32]
     L.labs_isl_batch_dev.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp]
     L.labs_enum_skew_dev.argtypes = [i32, vp, vp]
     L.labs_enum_skew_min.argtypes = [i32, u64, u64, P(EnumMinResult), vp]
@@ -276,6 +278,23 @@ def merit(s) -> float:
     out = ctypes.c_double()
     _check(lib().labs_merit(len(a), p, ctypes.byref(out)), "labs_merit")
     return out.value
+
+
+def from_hex(hexstr, L):
+    """labs_from_hex: Table 1's hex notation (Section 4) to L symbols +1 / -1 (numpy int8)."""
+    import numpy as np
+
+    out = np.empty(int(L), dtype=np.int8)
+    _check(lib().labs_from_hex(hexstr.encode(), int(L), out.ctypes.data), "labs_from_hex")
+    return out
+
+
+def to_hex(s) -> str:
+    """labs_to_hex: symbols +1 / -1 to Table 1's hex notation, ceil(L/4) upper-case digits."""
+    a, p = _host_i8(s)
+    buf = ctypes.create_string_buffer((len(a) + 3) // 4 + 1)
+    _check(lib().labs_to_hex(len(a), p, buf, len(buf)), "labs_to_hex")
+    return buf.value.decode()
 
 
 def isl_batch(s_dev, with_F=True, with_psl=True, with_corr=False):

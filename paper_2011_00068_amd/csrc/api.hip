@@ -241,6 +241,58 @@ extern "C" int labs_isl_threshold(int32_t L, int64_t num, int64_t den, int64_t *
     return LABS_OK;
 }
 
+// The sequence notation of Table 1 (Section 4): hex digits, 4 bits each with the most significant
+// first, leading zero bits dropped down to L symbols, bit 0 = +1 and bit 1 = -1.
+extern "C" int labs_from_hex(const char *hex, int32_t L, int8_t *s_out)
+{
+    if (!hex || !s_out || L < 1 || L > 65535)
+        return fail(LABS_EINVAL, "labs_from_hex: L = %d (need 1 <= L <= 65535) and non-NULL pointers", L);
+    const size_t nd = strlen(hex);
+    if (4 * (uint64_t)nd < (uint64_t)L)
+        return fail(LABS_EINVAL, "labs_from_hex: %zu digits do not hold %d symbols", nd, L);
+    // symbols from the last digit backwards: bit q (weight 2^q) of digit nd-1-d is symbol L-1-4d-q
+    for (size_t d = 0; d < nd; d++) {
+        const char ch = hex[nd - 1 - d];
+        const int v = (ch >= '0' && ch <= '9') ? ch - '0'
+                      : (ch >= 'a' && ch <= 'f') ? ch - 'a' + 10
+                      : (ch >= 'A' && ch <= 'F') ? ch - 'A' + 10 : -1;
+        if (v < 0)
+            return fail(LABS_EINVAL, "labs_from_hex: '%c' is not a hex digit", ch);
+        for (int q = 0; q < 4; q++) {
+            const int64_t i = (int64_t)L - 1 - 4 * (int64_t)d - q;
+            const int bit = (v >> q) & 1;
+            if (i >= 0)
+                s_out[i] = (int8_t)(1 - 2 * bit);
+            else if (bit)
+                return fail(LABS_EINVAL, "labs_from_hex: a dropped leading bit is 1 (more than %d symbols)", L);
+        }
+    }
+    return LABS_OK;
+}
+
+extern "C" int labs_to_hex(int32_t L, const int8_t *s, char *out, int32_t cap)
+{
+    if (!s || !out || L < 1 || L > 65535)
+        return fail(LABS_EINVAL, "labs_to_hex: L = %d (need 1 <= L <= 65535) and non-NULL pointers", L);
+    const int32_t nd = (L + 3) / 4;
+    if (cap < nd + 1)
+        return fail(LABS_EINVAL, "labs_to_hex: cap = %d, need %d", cap, nd + 1);
+    for (int32_t d = 0; d < nd; d++) {
+        int v = 0;
+        for (int q = 0; q < 4; q++) {
+            const int32_t i = L - 1 - 4 * d - q;
+            if (i < 0)
+                break;
+            if (s[i] != 1 && s[i] != -1)
+                return fail(LABS_EINVAL, "labs_to_hex: s[%d] = %d is not +1 or -1", i, s[i]);
+            v |= (s[i] < 0) << q;
+        }
+        out[nd - 1 - d] = "0123456789ABCDEF"[v];
+    }
+    out[nd] = '\0';
+    return LABS_OK;
+}
+
 extern "C" int labs_isl_batch_dev(int32_t L, int32_t count, const int8_t *s_dev, int64_t *isl_dev, double *F_dev,
                                   int32_t *psl_dev, int32_t *corr_dev, void *stream)
 {

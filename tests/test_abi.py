@@ -80,3 +80,63 @@ def test_isl_threshold_through_the_abi():
     for bad in ((0, 8, 1), (65536, 8, 1), (255, 0, 1), (255, 8, 0), (255, -1, 1)):
         assert thr(*bad)[0] == -1, bad
     assert f(255, 8, 1, None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="liblabs.so not built")
+def test_hex_codec_through_the_abi():
+    """labs_from_hex / labs_to_hex (Table 1's notation, Section 4) against the oracle's codec: all 52
+    printed rows, random sequences of every length 1..70 and of Table 1's lengths, and the error
+    cases.  Host code, so it runs without a GPU."""
+    import random
+
+    import numpy as np
+
+    from oracle import oracle as o
+    from tests import table1
+
+    lib = ctypes.CDLL(LIB)
+    lib.labs_from_hex.argtypes = [ctypes.c_char_p, ctypes.c_int32, ctypes.c_void_p]
+    lib.labs_to_hex.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int32]
+
+    def from_hex(h, L):
+        out = np.zeros(L, dtype=np.int8)
+        return lib.labs_from_hex(h.encode(), L, out.ctypes.data), out
+
+    def to_hex(s, cap=None):
+        a = np.ascontiguousarray(s, dtype=np.int8)
+        buf = ctypes.create_string_buffer((len(a) + 3) // 4 + 1 if cap is None else max(cap, 1))
+        rc = lib.labs_to_hex(len(a), a.ctypes.data, buf, (len(a) + 3) // 4 + 1 if cap is None else cap)
+        return rc, buf.value.decode()
+
+    for row in table1.rows():
+        rc, s = from_hex(row["hex"], row["L"])
+        assert rc == 0
+        assert np.array_equal(s, o.hex_decode(row["hex"], row["L"]))
+        assert from_hex(row["hex"].lower(), row["L"])[1].tolist() == s.tolist()
+        rc, h = to_hex(s)
+        assert rc == 0 and h == o.hex_encode(s)
+        assert h.lstrip("0") == row["hex"].lstrip("0")
+    rng = random.Random(2011000068)
+    for L in list(range(1, 71)) + list(range(201, 304, 2)):
+        s = np.array([rng.choice((1, -1)) for _ in range(L)], dtype=np.int8)
+        rc, h = to_hex(s)
+        assert rc == 0 and h == o.hex_encode(s) and len(h) == (L + 3) // 4
+        assert np.array_equal(from_hex(h, L)[1], s)
+        assert np.array_equal(from_hex("00" + h, L)[1], s)  # extra leading zero digits drop too
+    # symbol 0 is +1, 1 is -1, most significant bit first: "B" = 1011 -> - + - -
+    assert from_hex("B", 4)[1].tolist() == [-1, 1, -1, -1]
+    assert from_hex("3", 2)[1].tolist() == [-1, -1]
+    assert to_hex([1, -1, 1, 1, -1])[1] == "09"
+    EINVAL = -1
+    assert from_hex("F", 3)[0] == EINVAL  # a dropped leading bit is 1
+    assert from_hex("0", 5)[0] == EINVAL  # fewer bits than symbols
+    assert from_hex("0G", 5)[0] == EINVAL
+    assert from_hex("1", 0)[0] == EINVAL
+    assert to_hex([1, 0, -1])[0] == EINVAL
+    assert to_hex([1] * 8, cap=2)[0] == EINVAL  # 2 digits need 3 bytes
+    import paper_2011_00068_amd as labs
+
+    row = table1.rows()[27]
+    assert labs.to_hex(labs.from_hex(row["hex"], row["L"])) == o.hex_encode(o.hex_decode(row["hex"], row["L"]))
+    with pytest.raises(labs.LabsError):
+        labs.from_hex("F", 3)
