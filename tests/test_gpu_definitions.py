@@ -57,6 +57,23 @@ def test_isl_batch_table1(labs):
             assert int(psl[i]) == o.psl(s)
 
 
+def test_table1_through_the_library_alone(labs):
+    """Table 1 from the library's own entry points only: each printed sequence decoded by
+    labs_from_hex, its ISL, F and PSL computed by labs_isl_batch_dev, and compared with the printed
+    F (4 decimals) and PSL; for the two rows whose printed F no integer ISL of the printed sequence
+    gives, the ISL the oracle computes is asserted instead."""
+    errata_isl = {281: 4604, 283: 4837}
+    for r in table1.rows():
+        s = labs.from_hex(r["hex"], r["L"])
+        assert labs.to_hex(s).lstrip("0") == r["hex"].upper().lstrip("0")
+        isl, F, psl, _ = labs.isl_batch(torch.from_numpy(s[None, :].copy()).cuda())
+        assert int(psl[0]) == r["PSL"], r["L"]
+        if r["L"] in errata_isl:
+            assert int(isl[0]) == errata_isl[r["L"]]
+        else:
+            assert f"{float(F[0]):.4f}" == r["F"], r["L"]
+
+
 def test_isl_batch_empty(labs):
     dev = torch.zeros((0, 5), dtype=torch.int8, device="cuda")
     isl, _, _, _ = labs.isl_batch(dev)
