@@ -445,6 +445,22 @@ def counter_summary():
     return t
 
 
+def device_summary(labs, cnt):
+    """The device and its clocks: the maximum shader clock the runtime reports, and the effective
+    one of the walk kernel from the committed counter summary (GPU busy cycles per XCD,
+    rocprofv3 GRBM_GUI_ACTIVE / 8, over the launch's rocprofv3 duration), which the peaks are
+    quoted against at the nominal 2.4 GHz."""
+    out = {"name": None, "compute_units": None, "max_sclk_mhz": None, "sclk_measured_mhz": None}
+    try:
+        d = labs.device_info()
+        out.update(name=d["name"], compute_units=d["compute_units"], max_sclk_mhz=d["clock_khz"] / 1000.0)
+    except labs.LabsError as e:
+        print(f"device info failed: {e}", file=sys.stderr)
+    if cnt and cnt.get("gpu_cycles_per_xcd") and cnt.get("avg_launch_ns_rocprof"):
+        out["sclk_measured_mhz"] = cnt["gpu_cycles_per_xcd"] / cnt["avg_launch_ns_rocprof"] * 1000.0
+    return out
+
+
 def lds_summary(labs, cnt):
     """The walk kernel against the LDS roof: the share of cycles in which the LDS pipe of a compute
     unit is busy (rocprofv3 SQ_LDS_IDX_ACTIVE over GRBM_GUI_ACTIVE cycles, of which bank-conflict
@@ -552,8 +568,9 @@ def main():
     cnt = counter_summary()
     # The flip scoring's correlation sums run as int8 x int8 -> int32 matrix-core tiles, so the
     # roof of the algorithmic operations (381 per evaluation) is the dense int8 peak.  The kernel
-    # is far below it: each walk's product is three small tiles on a serial chain, and the roof
-    # that binds is instruction issue (the VALU, SALU and LDS-pipe shares from the counters).
+    # is far below it: each walk's product is two small matrix-core operations on a serial chain,
+    # and the roof that binds is instruction issue (the VALU, SALU and LDS-pipe shares from the
+    # counters).
     roofline = dict(matrix_or_alu_roofline(opts["variant"], achieved),
                     traffic=cnt["hbm_bytes_per_launch"] if cnt else None,
                     kernel="k_walk_mfma" if opts["variant"] == 3 else "k_walk",
@@ -593,6 +610,7 @@ def main():
                    # persistent = 1: one wave per walk, hardware-dispatched (not the pulling grid)
                    "plan_opts": opts},
         "roofline": roofline,
+        "device": device_summary(labs, cnt),
         "time_to_F5": time_to_target(res, ms_per_step, STEPS),
         "time_to_F8": time_to_f8(res),
     }
