@@ -272,6 +272,25 @@ def latency(labs, steps=200000):
     return out
 
 
+def shapes(labs, walks=16384, steps=2000):
+    """The one-tile and the two-tile matrix-core walker side by side (run with --only shapes, or
+    under rocprofv3 --pmc for their instructions per step): full-GPU batches of 16,384 walks x
+    2,000 steps at L = 255 (c = 127, one tile) and L = 303 (c = 151, two tiles); microseconds per
+    step of the launch (second run of each plan)."""
+    import torch
+
+    out = {"walks": walks, "steps": steps}
+    for Lx in (255, 303):
+        plan = labs.WalkPlan([labs.make_cfg(Lx, SEED, w, steps=steps, table_log2=TABLE_LOG2) for w in range(walks)])
+        plan.run()
+        torch.cuda.synchronize()
+        plan.run()
+        ms, _ = plan.last_timing()
+        plan.close()
+        out[f"L{Lx}_us_per_step"] = ms * 1000.0 / steps
+    return out
+
+
 def uneven_batch(labs):
     """Every odd L in [201, 303] x 64 walks x 10^6 steps in one launch of mixed shapes,
     replayed from a captured hipGraph."""
@@ -497,7 +516,7 @@ def main():
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
     ap.add_argument("--only", choices=["low_occupancy", "uneven_batch", "serving", "serving_F5", "serving_capacity",
                                        "enumeration",
-                                       "best_first", "general_walk", "first_improvement", "latency"],
+                                       "best_first", "general_walk", "first_improvement", "latency", "shapes"],
                     help="run only this measurement and print its JSON (for profiling)")
     ap.add_argument("--probe-lds", action="store_true",
                     help="only measure the LDS read bandwidth (4-, 8- and 16-byte reads per lane) and exit")
@@ -536,7 +555,7 @@ def main():
         legs = {"low_occupancy": low_occupancy, "uneven_batch": uneven_batch, "serving": serving,
                 "serving_F5": serving_f5,
                 "serving_capacity": serving_capacity, "first_improvement": first_improvement,
-                "latency": latency,
+                "latency": latency, "shapes": shapes,
                 "enumeration": enumeration, "best_first": best_first, "general_walk": general_walk}
         print(json.dumps({args.only: legs[args.only](labs)}), flush=True)
         return
