@@ -1,6 +1,7 @@
 // api.hip -- the C ABI of liblabs (include/labs.h): argument checking, device memory, launch
-// plans, hipGraph capture and the autotuner.  No computation happens on the CPU: every entry
-// point ends in the library's kernels.
+// plans, hipGraph capture and the autotuner.  No step of the search runs on the CPU: apart from
+// the conversions of a stop parameter and of sequence notation (labs_isl_threshold,
+// labs_from_hex, labs_to_hex), every entry point ends in the library's kernels.
 
 #include <algorithm>
 #include <cerrno>
@@ -250,21 +251,27 @@ extern "C" int labs_from_hex(const char *hex, int32_t L, int8_t *s_out)
     const size_t nd = strlen(hex);
     if (4 * (uint64_t)nd < (uint64_t)L)
         return fail(LABS_EINVAL, "labs_from_hex: %zu digits do not hold %d symbols", nd, L);
-    // symbols from the last digit backwards: bit q (weight 2^q) of digit nd-1-d is symbol L-1-4d-q
-    for (size_t d = 0; d < nd; d++) {
-        const char ch = hex[nd - 1 - d];
-        const int v = (ch >= '0' && ch <= '9') ? ch - '0'
-                      : (ch >= 'a' && ch <= 'f') ? ch - 'a' + 10
-                      : (ch >= 'A' && ch <= 'F') ? ch - 'A' + 10 : -1;
-        if (v < 0)
-            return fail(LABS_EINVAL, "labs_from_hex: '%c' is not a hex digit", ch);
-        for (int q = 0; q < 4; q++) {
-            const int64_t i = (int64_t)L - 1 - 4 * (int64_t)d - q;
-            const int bit = (v >> q) & 1;
-            if (i >= 0)
-                s_out[i] = (int8_t)(1 - 2 * bit);
-            else if (bit)
-                return fail(LABS_EINVAL, "labs_from_hex: a dropped leading bit is 1 (more than %d symbols)", L);
+    // symbols from the last digit backwards: bit q (weight 2^q) of digit nd-1-d is symbol L-1-4d-q;
+    // the first pass checks every digit and dropped bit, so that s_out is written only on success
+    auto digit = [](char ch) {
+        return (ch >= '0' && ch <= '9') ? ch - '0'
+               : (ch >= 'a' && ch <= 'f') ? ch - 'a' + 10
+               : (ch >= 'A' && ch <= 'F') ? ch - 'A' + 10 : -1;
+    };
+    for (int pass = 0; pass < 2; pass++) {
+        for (size_t d = 0; d < nd; d++) {
+            const char ch = hex[nd - 1 - d];
+            const int v = digit(ch);
+            if (v < 0)
+                return fail(LABS_EINVAL, "labs_from_hex: '%c' is not a hex digit", ch);
+            for (int q = 0; q < 4; q++) {
+                const int64_t i = (int64_t)L - 1 - 4 * (int64_t)d - q;
+                const int bit = (v >> q) & 1;
+                if (i < 0 && bit)
+                    return fail(LABS_EINVAL, "labs_from_hex: a dropped leading bit is 1 (more than %d symbols)", L);
+                if (pass == 1 && i >= 0)
+                    s_out[i] = (int8_t)(1 - 2 * bit);
+            }
         }
     }
     return LABS_OK;

@@ -129,6 +129,9 @@ def test_hex_codec_through_the_abi():
     assert to_hex([1, -1, 1, 1, -1])[1] == "09"
     EINVAL = -1
     assert from_hex("F", 3)[0] == EINVAL  # a dropped leading bit is 1
+    untouched = np.full(5, 7, dtype=np.int8)  # a failed decode leaves s_out as it was
+    assert lib.labs_from_hex(b"1G", 5, untouched.ctypes.data) == EINVAL and (untouched == 7).all()
+    assert lib.labs_from_hex(b"21", 5, untouched.ctypes.data) == EINVAL and (untouched == 7).all()
     assert from_hex("0", 5)[0] == EINVAL  # fewer bits than symbols
     assert from_hex("0G", 5)[0] == EINVAL
     assert from_hex("1", 0)[0] == EINVAL
