@@ -22,6 +22,8 @@
  *   - "host" pointers are ordinary CPU memory owned by the caller; the library copies out of /
  *     into them before returning.  "device" pointers are HIP device memory (hipMalloc or a torch
  *     CUDA tensor) owned by the caller; the library only reads / writes them.
+ *   - Entry points that run walks or searches take n_walks >= 1 (LABS_EINVAL for 0 or less,
+ *     checked before any device work); the batched sequence entry points accept count = 0.
  *   - stream: a hipStream_t passed as void*; NULL = the default (null) stream.  Entry points
  *     whose name ends in _dev are asynchronous on that stream unless stated otherwise; all
  *     others are synchronous.

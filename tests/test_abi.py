@@ -143,3 +143,20 @@ def test_hex_codec_through_the_abi():
     assert labs.to_hex(labs.from_hex(row["hex"], row["L"])) == o.hex_encode(o.hex_decode(row["hex"], row["L"]))
     with pytest.raises(labs.LabsError):
         labs.from_hex("F", 3)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="liblabs.so not built")
+def test_empty_walk_batches_are_refused_without_device_work():
+    """Every entry point that runs walks or searches refuses n_walks = 0 with LABS_EINVAL before it
+    touches a device, so the check holds on a CPU-only host too."""
+    lib = ctypes.CDLL(LIB)
+    vp = ctypes.c_void_p
+    EINVAL = -1
+    h = vp()
+    assert lib.labs_walk_plan_create(0, None, None, ctypes.byref(h)) == EINVAL
+    assert lib.labs_walk_batch(0, None, None, None, None, None) == EINVAL
+    opts = (ctypes.c_int32 * 16)()  # non-NULL options; only n_walks is at fault
+    assert lib.labs_pq_walk_batch(0, None, opts, None, None, None, None, None) == EINVAL
+    assert lib.labs_fi_walk_batch(0, None, opts, None, None, None, None, None) == EINVAL
+    assert lib.labs_general_walk_batch(0, None, None, None, None, None, None) == EINVAL
+    assert lib.labs_walk_plan_create(-3, None, None, ctypes.byref(h)) == EINVAL
