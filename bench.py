@@ -141,7 +141,22 @@ def cpu_baseline(budget_s=10.0):
     return {"value": flips / dt, "unit": "flip-evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(res)} of the {WALKS} walks, all {STEPS} steps each, L={L}, "
                       f"{threads} threads; {dt:.1f} s wall",
-            "one_thread": {"value": one_flips / dt1 if dt1 > 0 else None, "walks": one_walks}}, res
+            "one_thread": {"value": one_flips / dt1 if dt1 > 0 else None, "walks": one_walks},
+            "host": host_cpu()}, res
+
+
+def host_cpu():
+    """The host CPU the oracle ran on: model name and the logical CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus_available": len(os.sched_getaffinity(0))}
 
 
 def plain_form(labs, walks=32):
