@@ -3,7 +3,9 @@
 oracle, and the uneven batch of every odd L in
 [201, 303] x 64 walks x 10^6 steps in one launch, checked by properties that hold at any size
 (each walk's best / final ISL is the ISL of its best / final bits, evaluation counts) and by
-invariance under splitting the walks over several launches."""
+invariance under splitting the walks over several launches, with sampled long walks against the
+oracle; and full-GPU batches of 16,384 walks of the one-tile (L = 255) and two-tile (L = 303)
+matrix-core walker with sampled walks against the oracle."""
 import numpy as np
 import pytest
 
@@ -107,3 +109,34 @@ def test_uneven_batch_long_walks_match_oracle(labs):
         for k in ("best_isl", "best_step", "steps_done", "flip_evals", "hit_step", "watch_step", "final_isl",
                   "restarts", "traps", "best_bits", "final_bits"):
             assert got[k] == ref[k], (L, w, k, got[k], ref[k])
+
+
+@pytest.mark.parametrize("L", [255, 303])  # the one-tile and the two-tile matrix-core walker
+def test_full_gpu_batches_of_each_walker_shape(labs, L):
+    # The batches that compare the two walker shapes (16,384 walks x 2,000 steps, two rounds of
+    # resident waves): 12 walks spread over the grid (first, last and the round boundaries) against
+    # the oracle in every result field, and every walk's best / final ISL against the ISL of its
+    # best / final bits.
+    from concurrent.futures import ThreadPoolExecutor
+
+    walks, steps = 16384, 2000
+    cfgs = [labs.make_cfg(L, SEED, w, steps=steps, table_log2=16) for w in range(walks)]
+    plan = labs.WalkPlan(cfgs)
+    assert plan.opts()["variant"] == labs.VARIANT_MFMA
+    plan.run()
+    plan.run()  # the second run, as timed: tables reused under new epochs
+    res = plan.results()
+    plan.close()
+    picks = [0, 1, 4095, 4096, 5119, 5120, 8191, 8192, 10239, 12288, 16382, 16383]
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        refs = list(ex.map(lambda w: o.walk(L, SEED, w, steps=steps, table_log2=16), picks))
+    for w, ref in zip(picks, refs):
+        for k in ("best_isl", "best_step", "steps_done", "flip_evals", "hit_step", "watch_step", "final_isl",
+                  "restarts", "traps", "best_bits", "final_bits"):
+            assert res[w][k] == ref[k], (L, w, k, res[w][k], ref[k])
+    rng = np.random.default_rng(L)
+    for w in rng.choice(walks, 64, replace=False):
+        r = res[int(w)]
+        assert r["steps_done"] == steps and r["flip_evals"] == steps * ((L + 1) // 2)
+        assert o.isl(o.skew_expand(L, r["best_bits"])) == r["best_isl"]
+        assert o.isl(o.skew_expand(L, r["final_bits"])) == r["final_isl"]
