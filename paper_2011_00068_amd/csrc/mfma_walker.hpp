@@ -552,6 +552,9 @@ struct MfmaWalker {
     // whether a walk takes commit_read for its best candidate during the probe: measured faster for
     // c <= 63 (L = 101: 4.6 % per step), slower for the longer shapes, whose registers it crowds
     static constexpr bool kSpecRead = KW <= 2 && !BIG;
+    // issue priority for the commit phase (see IssuePrioOf): the one-tile shape of the widest
+    // window (c <= 127, the L = 193 .. 255 walks) in a launch of that shape alone
+    static constexpr bool kIssuePrio = KW == 4 && !BIG && std::is_same<LdsT, WaveLdsMfma>::value;
 
     __device__ __forceinline__ CommitRead commit_read(int js) const
     {
